@@ -1,0 +1,139 @@
+/*
+ * ddqcd: SAP-preconditioned flexible GCR solver for the Wilson-clover Dirac
+ * equation on one AMD MI355X (gfx950), after Heybrock et al., "Lattice QCD
+ * with Domain Decomposition on Intel Xeon Phi Co-Processors", SC14
+ * (arXiv:1412.2629).
+ *
+ * The operator (Sec. II-B, Eqs. 1-3):
+ *   A = (4 + m) - D_w / 2 + D_cl,    4 + m = 1 / (2 kappa),
+ *   D_w psi(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *              + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu),
+ *   D_cl = c_sw sum_{mu,nu} (i/8) sigma_munu F_munu   (clover-leaf field strength),
+ * gamma matrices in the chiral basis (the clover term is then two Hermitian
+ * 6x6 blocks per site), mu = 0..3 <-> x, y, z, t.  A hop that wraps around
+ * the lattice in direction mu is multiplied by boundary[mu] (+1 or -1).
+ *
+ * The solver (Sec. II-C, II-D and the algorithm of Table I): flexible GCR
+ * with restart, right-preconditioned by the Schwarz alternating procedure
+ * (multiplicative Schwarz over a black/white colouring of the domains), each
+ * block solved approximately by minimal-residual (MR) steps on the even-odd
+ * Schur complement (Sec. II-D, Eq. 5).  The outer solver, its residuals and
+ * the solution update are FP64; the preconditioner runs in FP64, FP32, or
+ * FP32 arithmetic with FP16 storage (Sec. III, III-B).
+ *
+ * Canonical layouts at this interface (all device pointers, C-contiguous):
+ *   site index      i = x + Lx*(y + Ly*(z + Lz*t))
+ *   gauge field     double[V][4][3][3][2]   U_mu(x)[row][col], re/im interleaved
+ *   spinor field    double[nrhs][V][4][3][2] psi(x)[spin][colour]
+ * Pointers must be 16-byte aligned device memory of the current device.
+ *
+ * Ownership: the caller owns every pointer it passes.  The library owns the
+ * device memory it allocates for a context (internal copies of the links,
+ * clover terms, solver work vectors) and frees it in ddqcd_destroy.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  apply_D
+ * and sap are asynchronous on that stream; load_gauge and solve return
+ * after the stream has drained (solve reads residual norms on the host).
+ *
+ * Errors: every entry point returns a ddqcd_status; nothing throws across
+ * the interface.  ddqcd_last_error(ctx) describes the last failure.
+ * One context must not be used by two host threads at once.
+ */
+#ifndef DDQCD_H
+#define DDQCD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddqcd_ctx *ddqcd_t;
+
+typedef enum {
+    DDQCD_OK = 0,
+    DDQCD_ERR_ARG = 1,           /* bad argument (null pointer, kappa <= 0, |boundary| != 1, ...) */
+    DDQCD_ERR_GEOMETRY = 2,      /* domain shape does not tile the lattice in an even count >= 2 per direction,
+                                    an odd domain extent, or a domain shape without a compiled kernel */
+    DDQCD_ERR_STATE = 3,         /* call out of order (e.g. solve before load_gauge) */
+    DDQCD_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    DDQCD_ERR_NOMEM = 5,         /* device allocation failed */
+    DDQCD_ERR_NOT_CONVERGED = 6, /* solve stopped at max_cycles; x holds the last iterate */
+    DDQCD_ERR_NONFINITE = 7      /* NaN or Inf in the input or in a residual */
+} ddqcd_status;
+
+typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2 } ddqcd_prec;
+
+typedef struct {
+    int converged;        /* 1 if |b - A x| / |b| <= tol */
+    int iters;            /* FGCR steps (= preconditioner applications) */
+    int restarts;         /* FGCR cycles */
+    double rel_residual;  /* true residual |b - A x| / |b|, recomputed in FP64 at exit */
+    double t_total_ms;    /* wall time of the call */
+    double t_sap_ms;      /* preconditioner M (stream time, events) */
+    double t_A_ms;        /* operator A */
+    double t_gs_ms;       /* Gram-Schmidt */
+    double t_other_ms;    /* remaining linear algebra */
+} ddqcd_info;
+
+/* Creates a context for one lattice (host metadata only; no device memory).
+ * lattice[4]: Lx, Ly, Lz, Lt.  domain[4]: Schwarz domain extents; each must be
+ * even, divide the lattice extent, and leave an even number >= 2 of domains
+ * per direction (black/white colouring of Sec. IV-B2).  kappa > 0 gives
+ * 4 + m = 1/(2 kappa) (Sec. II-B).  boundary[mu] in {+1, -1}.
+ * Defaults: SAP 16 cycles, 5 MR steps, FP32 (Sec. IV-C); FGCR restart 16,
+ * tol 1e-10, max 64 cycles.  Returns DDQCD_ERR_GEOMETRY / DDQCD_ERR_ARG on
+ * invalid input; *out is set only on success. */
+int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double c_sw, const double boundary[4],
+                 ddqcd_t *out);
+
+/* Frees the context and all device memory it owns.  NULL is allowed. */
+int ddqcd_destroy(ddqcd_t ctx);
+
+/* Schwarz preconditioner settings: n_cycles = I_Schwarz >= 1, n_mr = I_domain
+ * >= 1 (Sec. II-D), prec = storage/arithmetic of the block solves:
+ * DDQCD_FP64, DDQCD_FP32, or DDQCD_FP16 (FP16 links, clover and spinors with
+ * per-domain scales, FP32 arithmetic, FP32 solution accumulator).  FP64 is
+ * available for 2x2x2x2 domains only (DDQCD_ERR_GEOMETRY otherwise). */
+int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec);
+
+/* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the
+ * true relative residual |b - A x|/|b| (Sec. IV-C1), max_cycles >= 1. */
+int ddqcd_set_solver(ddqcd_t ctx, int restart, double tol, int max_cycles);
+
+/* Loads the gauge field U (device pointer, canonical layout, FP64), builds the
+ * clover term (Sec. II-B, Eq. 3), its odd-site inverse (needed by the Schur
+ * complement of Sec. II-D, Eq. 5) and the reduced-precision copies.  The
+ * caller may reuse U once this returns.  Allocates the context's device
+ * memory on the current device on first call. */
+int ddqcd_load_gauge(ddqcd_t ctx, const double *U, void *stream);
+
+/* out = A in for nrhs spinor fields (canonical layout, FP64 at the interface).
+ * prec selects the arithmetic and storage of the application: DDQCD_FP64, or
+ * DDQCD_FP32 / DDQCD_FP16 (input rounded to that precision, 2-row compressed
+ * links, result rounded before widening to FP64).  in and out must not alias. */
+int ddqcd_apply_D(ddqcd_t ctx, double *out, const double *in, int nrhs, int prec, void *stream);
+
+/* out = M in: the Schwarz alternating procedure with the settings of
+ * ddqcd_set_sap (Sec. II-D; the algorithm of Table I without the outer loop).
+ * in and out must not alias. */
+int ddqcd_sap(ddqcd_t ctx, double *out, const double *in, int nrhs, void *stream);
+
+/* Solves A x = b for nrhs right-hand sides with SAP-preconditioned FGCR.  If
+ * x_is_guess, x holds the initial guess; else it starts from zero.  info
+ * (optional) receives nrhs records.  Returns DDQCD_OK when every right-hand
+ * side converged, DDQCD_ERR_NOT_CONVERGED otherwise (x then holds the last
+ * iterate).  b and x must not alias. */
+int ddqcd_solve(ddqcd_t ctx, double *x, const double *b, int nrhs, int x_is_guess, ddqcd_info *info, void *stream);
+
+/* Text of the last error on this context (never NULL; "" if none). */
+const char *ddqcd_last_error(ddqcd_t ctx);
+
+/* Name of a status code. */
+const char *ddqcd_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDQCD_H */

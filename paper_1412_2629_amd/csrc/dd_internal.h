@@ -1,0 +1,84 @@
+// Host-side interface between the C-ABI layer and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dd_device.h"
+
+namespace dd {
+
+enum { P64 = 0, P32 = 1, P16 = 2 };
+
+// Canonical FP64 spinor [V][12] complex <-> internal layout in precision prec.
+hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int prec, hipStream_t s);
+hipError_t export_spinor(const Geo &g, const void *internal, int prec, double *canon, hipStream_t s);
+
+// Canonical FP64 links -> internal FP64 full links [d][mu][9][Vd].
+hipError_t import_gauge(const Geo &g, const double *canon, double2 *U64, hipStream_t s);
+// Internal FP64 full links -> first two rows in FP32 or FP16 [d][mu][6][Vd].
+hipError_t compress_links(const Geo &g, const double2 *U64, void *out, int prec, hipStream_t s);
+// Clover term C(x) = 1/(2 kappa) + D_cl(x), packed [d][36][Vd] FP64.
+hipError_t clover_build(const Geo &g, const double2 *U64, double kappa, double csw, double2 *C64, hipStream_t s);
+// Site matrices used by the block solves: C on even sites, C^-1 on odd sites.
+// *bad (device int) is set to 1 if a block is singular.
+hipError_t clover_schur(const Geo &g, const double2 *C64, double2 *Cs64, int *bad, hipStream_t s);
+// Elementwise FP64 pairs -> FP32 / FP16 pairs.
+hipError_t convert_pairs(const double2 *in, void *out, long n, int prec, hipStream_t s);
+// Number of non-finite values in n FP64 pairs (device counter *cnt, accumulated).
+hipError_t count_nonfinite(const double2 *v, long n, int *cnt, hipStream_t s);
+
+// out = A in (internal layouts; links/clover in the given precision).
+hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
+                   hipStream_t s);
+
+// One SAP half-sweep over the domains of one colour.
+struct SapArgs {
+    Geo g;
+    const int *dom;     // domains of the colour being swept
+    int ndom;
+    int first;          // first visit of these domains: residual is eta
+    int faces_in;       // add the boundary terms of the previous half-sweep
+    int last;           // last visit: write psi (+ delta) to out
+    int faces_out;      // write this sweep's boundary terms
+    int res_out;        // store the block residual
+    int n_mr;
+    const double2 *eta; // FP64 input of the preconditioner
+    double2 *out;       // FP64 output
+    void *psi;          // solution accumulator (FP64, or FP32 for FP32/FP16 storage)
+    void *res;          // block residual on even sites [d][12][Vd/2]
+    float *res_scale;   // per-domain scale of res (FP16 storage)
+    void *face;         // boundary half-spinors [d][8 faces][6][face sites]
+    float *face_scale;  // per-domain scale of face (FP16 storage)
+    const void *links;  // [d][mu][9 or 6][Vd]
+    const void *cs;     // C_e on even / C_o^-1 on odd sites [d][36][Vd]
+    void *rho_tmp;      // odd-site right-hand sides [d][12][Vd/2] when not kept in LDS
+};
+bool sap_shape_supported(const int b[4]);
+bool sap_prec_supported(const int b[4], int prec);
+long sap_face_sites(const int b[4]);
+hipError_t sap_sweep(const SapArgs &a, int prec, hipStream_t s);
+
+// ---- FP64 linear algebra on flat complex vectors (double2) ---------------
+struct Blas {
+    double2 *partial = nullptr;   // [NBLK][32]
+    double2 *result = nullptr;    // [32] device
+    double2 *coef = nullptr;      // [32] device coefficients
+    hipError_t init();
+    void release();
+};
+enum { BLAS_NBLK = 1024, BLAS_MAXK = 16 };
+// result[j] = <W_j, v>, j < k (k <= 16); W_j = W + j*ldw
+hipError_t multidot(Blas &B, const double2 *W, long ldw, int k, const double2 *v, long n, hipStream_t s);
+// w -= sum_j coef[j] W_j (coef on device, k <= 16); result[0] = (|w|^2, 0), result[1] = <w, r>
+hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, const double2 *r, long n,
+                      hipStream_t s);
+// w *= inv_b; r -= c w; result[0] = (|r|^2, 0)
+hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s);
+// x += sum_j coef[j] Z_j (coef on device, k <= 16)
+hipError_t axpy_multi(Blas &B, double2 *x, const double2 *Z, long ldz, int k, long n, hipStream_t s);
+// r = b - r; result[0] = (|r|^2, 0)
+hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s);
+// result[0] = (|v|^2, 0)
+hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s);
+hipError_t zero(double2 *v, long n, hipStream_t s);
+
+}  // namespace dd

@@ -1,0 +1,644 @@
+// Layout conversion, clover set-up, the global operator A and the FP64
+// linear algebra of the outer solver.
+#include <hip/hip_runtime.h>
+
+#include "dd_device.h"
+#include "dd_internal.h"
+
+namespace dd {
+
+static inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ===========================================================================
+// layout conversion
+// ===========================================================================
+
+__device__ __forceinline__ long canon_index(const Geo &g, const int x[4])
+{
+    return x[0] + (long)g.L[0] * (x[1] + (long)g.L[1] * (x[2] + (long)g.L[2] * x[3]));
+}
+
+template <typename S> __global__ void k_import_spinor(Geo g, const double2 *canon, v2<S> *out)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    long c = canon_index(g, x) * 12;
+#pragma unroll
+    for (int k = 0; k < 12; k++) st<double, S>(out, ((long)d * 12 + k) * g.Vd + loc, ld<double, double>(canon, c + k));
+}
+
+template <typename S> __global__ void k_export_spinor(Geo g, const v2<S> *in, double2 *canon)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    long c = canon_index(g, x) * 12;
+#pragma unroll
+    for (int k = 0; k < 12; k++) st<double, double>(canon, c + k, ld<double, S>(in, ((long)d * 12 + k) * g.Vd + loc));
+}
+
+hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int prec, hipStream_t s)
+{
+    unsigned nb = nblocks(g.V, 256);
+    if (prec == P64) hipLaunchKernelGGL(k_import_spinor<double>, nb, 256, 0, s, g, (const double2 *)canon, (double2 *)internal);
+    else if (prec == P32) hipLaunchKernelGGL(k_import_spinor<float>, nb, 256, 0, s, g, (const double2 *)canon, (float2 *)internal);
+    else hipLaunchKernelGGL(k_import_spinor<half_t>, nb, 256, 0, s, g, (const double2 *)canon, (half2_t *)internal);
+    return hipGetLastError();
+}
+
+hipError_t export_spinor(const Geo &g, const void *internal, int prec, double *canon, hipStream_t s)
+{
+    unsigned nb = nblocks(g.V, 256);
+    if (prec == P64) hipLaunchKernelGGL(k_export_spinor<double>, nb, 256, 0, s, g, (const double2 *)internal, (double2 *)canon);
+    else if (prec == P32) hipLaunchKernelGGL(k_export_spinor<float>, nb, 256, 0, s, g, (const float2 *)internal, (double2 *)canon);
+    else hipLaunchKernelGGL(k_export_spinor<half_t>, nb, 256, 0, s, g, (const half2_t *)internal, (double2 *)canon);
+    return hipGetLastError();
+}
+
+__global__ void k_import_gauge(Geo g, const double2 *canon, double2 *U)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    long c = canon_index(g, x) * 36;
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+        for (int e = 0; e < 9; e++) U[(((long)d * 4 + mu) * 9 + e) * g.Vd + loc] = canon[c + mu * 9 + e];
+}
+
+hipError_t import_gauge(const Geo &g, const double *canon, double2 *U64, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_import_gauge, nblocks(g.V, 256), 256, 0, s, g, (const double2 *)canon, U64);
+    return hipGetLastError();
+}
+
+template <typename S> __global__ void k_compress_links(Geo g, const double2 *U, v2<S> *out)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int d = (int)(I / g.Vd), loc = (int)(I - (long)d * g.Vd);
+    for (int mu = 0; mu < 4; mu++)
+#pragma unroll
+        for (int e = 0; e < 6; e++)
+            st<double, S>(out, (((long)d * 4 + mu) * 6 + e) * g.Vd + loc,
+                          ld<double, double>(U, (((long)d * 4 + mu) * 9 + e) * g.Vd + loc));
+}
+
+hipError_t compress_links(const Geo &g, const double2 *U64, void *out, int prec, hipStream_t s)
+{
+    unsigned nb = nblocks(g.V, 256);
+    if (prec == P32) hipLaunchKernelGGL(k_compress_links<float>, nb, 256, 0, s, g, U64, (float2 *)out);
+    else hipLaunchKernelGGL(k_compress_links<half_t>, nb, 256, 0, s, g, U64, (half2_t *)out);
+    return hipGetLastError();
+}
+
+template <typename S> __global__ void k_convert_pairs(const double2 *in, v2<S> *out, long n)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) st<double, S>(out, i, ld<double, double>(in, i));
+}
+
+hipError_t convert_pairs(const double2 *in, void *out, long n, int prec, hipStream_t s)
+{
+    unsigned nb = nblocks(n, 256);
+    if (prec == P32) hipLaunchKernelGGL(k_convert_pairs<float>, nb, 256, 0, s, in, (float2 *)out, n);
+    else hipLaunchKernelGGL(k_convert_pairs<half_t>, nb, 256, 0, s, in, (half2_t *)out, n);
+    return hipGetLastError();
+}
+
+__global__ void k_count_nonfinite(const double2 *v, long n, int *cnt)
+{
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    for (; i < n; i += (long)gridDim.x * blockDim.x) bad |= !isfinite(v[i].x) || !isfinite(v[i].y);
+    if (bad) atomicOr(cnt, 1);
+}
+
+hipError_t count_nonfinite(const double2 *v, long n, int *cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_nonfinite, 1024, 256, 0, s, v, n, cnt);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// clover term (Sec. II-B, Eq. 3) and its odd-site inverse (Sec. II-D, Eq. 5)
+// ===========================================================================
+
+struct m3 {
+    cx<double> e[9];
+};
+
+__device__ __forceinline__ m3 m3_load(const Geo &g, const double2 *U, const int x[4], int mu)
+{
+    long J = encode(g, x);
+    int d = (int)(J / g.Vd), loc = (int)(J - (long)d * g.Vd);
+    m3 r;
+    for (int e = 0; e < 9; e++) r.e[e] = ld<double, double>(U, (((long)d * 4 + mu) * 9 + e) * g.Vd + loc);
+    return r;
+}
+
+// a * b with optional daggers
+__device__ __forceinline__ m3 m3_mul(const m3 &a, bool da, const m3 &b, bool db)
+{
+    m3 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cx<double> s = czero<double>();
+            for (int k = 0; k < 3; k++) {
+                cx<double> av = da ? cx<double>{a.e[k * 3 + i].r, -a.e[k * 3 + i].i} : a.e[i * 3 + k];
+                cx<double> bv = db ? cx<double>{b.e[j * 3 + k].r, -b.e[j * 3 + k].i} : b.e[k * 3 + j];
+                s = s + av * bv;
+            }
+            r.e[i * 3 + j] = s;
+        }
+    return r;
+}
+
+__device__ __forceinline__ void shift(const Geo &g, const int x[4], int mu, int step, int y[4])
+{
+    for (int m = 0; m < 4; m++) y[m] = x[m];
+    y[mu] += step;
+    if (y[mu] >= g.L[mu]) y[mu] -= g.L[mu];
+    if (y[mu] < 0) y[mu] += g.L[mu];
+}
+
+// F_munu = (Q - Q^dag) / 8, Q = sum of the four leaves at x oriented mu -> nu
+__device__ m3 field_strength(const Geo &g, const double2 *U, const int x[4], int mu, int nu)
+{
+    int xpm[4], xmm[4], xpn[4], xmn[4], a[4], b[4], c[4];
+    shift(g, x, mu, +1, xpm);
+    shift(g, x, mu, -1, xmm);
+    shift(g, x, nu, +1, xpn);
+    shift(g, x, nu, -1, xmn);
+    shift(g, xpn, mu, -1, a);   // x + nu - mu
+    shift(g, xmm, nu, -1, b);   // x - mu - nu
+    shift(g, xmn, mu, +1, c);   // x - nu + mu
+    m3 Q, t;
+    // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+    t = m3_mul(m3_load(g, U, x, mu), false, m3_load(g, U, xpm, nu), false);
+    t = m3_mul(t, false, m3_load(g, U, xpn, mu), true);
+    Q = m3_mul(t, false, m3_load(g, U, x, nu), true);
+    // leaf 2: U_nu(x) U_mu(x+nu-mu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+    t = m3_mul(m3_load(g, U, x, nu), false, m3_load(g, U, a, mu), true);
+    t = m3_mul(t, false, m3_load(g, U, xmm, nu), true);
+    t = m3_mul(t, false, m3_load(g, U, xmm, mu), false);
+    for (int e = 0; e < 9; e++) Q.e[e] = Q.e[e] + t.e[e];
+    // leaf 3: U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+    t = m3_mul(m3_load(g, U, xmm, mu), true, m3_load(g, U, b, nu), true);
+    t = m3_mul(t, false, m3_load(g, U, b, mu), false);
+    t = m3_mul(t, false, m3_load(g, U, xmn, nu), false);
+    for (int e = 0; e < 9; e++) Q.e[e] = Q.e[e] + t.e[e];
+    // leaf 4: U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
+    t = m3_mul(m3_load(g, U, xmn, nu), true, m3_load(g, U, xmn, mu), false);
+    t = m3_mul(t, false, m3_load(g, U, c, nu), false);
+    t = m3_mul(t, false, m3_load(g, U, x, mu), true);
+    for (int e = 0; e < 9; e++) Q.e[e] = Q.e[e] + t.e[e];
+    m3 F;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            cx<double> q = Q.e[i * 3 + j], qd = {Q.e[j * 3 + i].r, -Q.e[j * 3 + i].i};
+            F.e[i * 3 + j] = scal(0.125, q - qd);
+        }
+    return F;
+}
+
+// In the chiral basis sigma_jk = -eps_jkl diag(s_l, s_l) (j,k spatial) and
+// sigma_kt = diag(-s_k, s_k), so with E_l the colour matrices multiplying
+// s_l, each chiral block of D_cl is [[E3, E1 - i E2], [E1 + i E2, -E3]] with
+//   upper: E1 = -(i c/2)(F_yz + F_xt), E2 = (i c/2)(F_xz - F_yt), E3 = -(i c/2)(F_xy + F_zt)
+//   lower: E1 = -(i c/2)(F_yz - F_xt), E2 = (i c/2)(F_xz + F_yt), E3 = -(i c/2)(F_xy - F_zt)
+__global__ void k_clover_build(Geo g, const double2 *U, double kappa, double csw, double2 *C)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    m3 Fxy = field_strength(g, U, x, 0, 1), Fxz = field_strength(g, U, x, 0, 2), Fxt = field_strength(g, U, x, 0, 3);
+    m3 Fyz = field_strength(g, U, x, 1, 2), Fyt = field_strength(g, U, x, 1, 3), Fzt = field_strength(g, U, x, 2, 3);
+    const double diag = 1.0 / (2.0 * kappa);
+    for (int blk = 0; blk < 2; blk++) {
+        const double sg = blk == 0 ? 1.0 : -1.0;
+        cx<double> M[6][6];
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                int e = i * 3 + j;
+                // -(i c/2) X = (c/2) (X.i, -X.r)
+                cx<double> s1 = Fyz.e[e] + scal(sg, Fxt.e[e]);
+                cx<double> s2 = Fxz.e[e] - scal(sg, Fyt.e[e]);
+                cx<double> s3 = Fxy.e[e] + scal(sg, Fzt.e[e]);
+                cx<double> E1 = scal(0.5 * csw, cx<double>{s1.i, -s1.r});
+                cx<double> E2 = scal(0.5 * csw, cx<double>{-s2.i, s2.r});
+                cx<double> E3 = scal(0.5 * csw, cx<double>{s3.i, -s3.r});
+                M[i][j] = E3;
+                M[3 + i][3 + j] = neg(E3);
+                M[i][3 + j] = E1 - times_i(E2);
+                M[3 + i][j] = E1 + times_i(E2);
+            }
+        for (int i = 0; i < 6; i++) M[i][i].r += diag;
+        long base = ((long)d * 36 + blk * 18) * g.Vd + loc;
+        for (int q = 0; q < 3; q++) C[base + q * g.Vd] = make_double2(M[2 * q][2 * q].r, M[2 * q + 1][2 * q + 1].r);
+        for (int i = 1; i < 6; i++)
+            for (int j = 0; j < i; j++) C[base + (3 + tri_index(i, j)) * g.Vd] = make_double2(M[i][j].r, M[i][j].i);
+    }
+}
+
+hipError_t clover_build(const Geo &g, const double2 *U64, double kappa, double csw, double2 *C64, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clover_build, nblocks(g.V, 128), 128, 0, s, g, U64, kappa, csw, C64);
+    return hipGetLastError();
+}
+
+// one thread per (site, chiral block): copy on even sites, Gauss-Jordan
+// inverse with partial pivoting on odd sites
+__global__ void k_clover_schur(Geo g, const double2 *C, double2 *Cs, int *bad)
+{
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * g.V) return;
+    long I = t >> 1;
+    int blk = (int)(t & 1);
+    int d = (int)(I / g.Vd), loc = (int)(I - (long)d * g.Vd);
+    long base = ((long)d * 36 + blk * 18) * g.Vd + loc;
+    if (loc < g.Vh) {
+        for (int q = 0; q < 18; q++) Cs[base + q * g.Vd] = C[base + q * g.Vd];
+        return;
+    }
+    cx<double> M[6][12];
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 12; j++) M[i][j] = czero<double>();
+    for (int q = 0; q < 3; q++) {
+        double2 v = C[base + q * g.Vd];
+        M[2 * q][2 * q].r = v.x;
+        M[2 * q + 1][2 * q + 1].r = v.y;
+    }
+    for (int i = 1; i < 6; i++)
+        for (int j = 0; j < i; j++) {
+            double2 v = C[base + (3 + tri_index(i, j)) * g.Vd];
+            M[i][j] = {v.x, v.y};
+            M[j][i] = {v.x, -v.y};
+        }
+    for (int i = 0; i < 6; i++) M[i][6 + i].r = 1.0;
+    for (int c = 0; c < 6; c++) {
+        int p = c;
+        double best = M[c][c].r * M[c][c].r + M[c][c].i * M[c][c].i;
+        for (int r = c + 1; r < 6; r++) {
+            double v = M[r][c].r * M[r][c].r + M[r][c].i * M[r][c].i;
+            if (v > best) { best = v; p = r; }
+        }
+        if (!(best > 0)) { atomicOr(bad, 1); return; }
+        if (p != c)
+            for (int j = 0; j < 12; j++) { cx<double> tmp = M[c][j]; M[c][j] = M[p][j]; M[p][j] = tmp; }
+        cx<double> piv = M[c][c];
+        double inv = 1.0 / best;
+        cx<double> ip = {piv.r * inv, -piv.i * inv};
+        for (int j = 0; j < 12; j++) M[c][j] = M[c][j] * ip;
+        for (int r = 0; r < 6; r++) {
+            if (r == c) continue;
+            cx<double> f = M[r][c];
+            for (int j = 0; j < 12; j++) M[r][j] = M[r][j] - f * M[c][j];
+        }
+    }
+    for (int q = 0; q < 3; q++) Cs[base + q * g.Vd] = make_double2(M[2 * q][6 + 2 * q].r, M[2 * q + 1][6 + 2 * q + 1].r);
+    for (int i = 1; i < 6; i++)
+        for (int j = 0; j < i; j++) {
+            // Hermitian inverse: average the two triangles to remove rounding asymmetry
+            cx<double> a = M[i][6 + j], b = M[j][6 + i];
+            Cs[base + (3 + tri_index(i, j)) * g.Vd] = make_double2(0.5 * (a.r + b.r), 0.5 * (a.i - b.i));
+        }
+}
+
+hipError_t clover_schur(const Geo &g, const double2 *C64, double2 *Cs64, int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clover_schur, nblocks(2 * g.V, 128), 128, 0, s, g, C64, Cs64, bad);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// global operator A (Sec. II-B, Eqs. 1-2): one thread per site
+// ===========================================================================
+
+template <int MU, typename T, typename SI, typename G, int NLC>
+__device__ __forceinline__ void a_hops(const Geo &g, const int x[4], int d, int loc, const v2<SI> *in,
+                                       const v2<G> *links, cx<T> acc[12])
+{
+    const long Vd = g.Vd;
+    int y[4] = {x[0], x[1], x[2], x[3]};
+    cx<T> v[12], h[6], uh[6];
+    // forward: -1/2 (1 - gamma_mu) U_mu(x) psi(x + mu)
+    bool wrap = false;
+    y[MU] = x[MU] + 1;
+    if (y[MU] == g.L[MU]) { y[MU] = 0; wrap = true; }
+    long J = encode(g, y);
+    int dj = (int)(J / Vd), lj = (int)(J - (long)dj * Vd);
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = ld<T, SI>(in, ((long)dj * 12 + k) * Vd + lj);
+    proj<MU, -1>(v, h);
+    {
+        su3<T> U = ld_link<T, G, NLC>(links, ((long)d * 4 + MU) * NLC * Vd + loc, Vd);
+        su3_mul(U, h, uh);
+    }
+    recon_acc<MU, -1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
+    // backward: -1/2 (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
+    wrap = false;
+    y[MU] = x[MU] - 1;
+    if (y[MU] < 0) { y[MU] = g.L[MU] - 1; wrap = true; }
+    J = encode(g, y);
+    dj = (int)(J / Vd);
+    lj = (int)(J - (long)dj * Vd);
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = ld<T, SI>(in, ((long)dj * 12 + k) * Vd + lj);
+    proj<MU, +1>(v, h);
+    {
+        su3<T> U = ld_link<T, G, NLC>(links, ((long)dj * 4 + MU) * NLC * Vd + lj, Vd);
+        su3_dag_mul(U, h, uh);
+    }
+    recon_acc<MU, +1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
+}
+
+template <typename T, typename SI, typename SO, typename G, int NLC>
+__global__ __launch_bounds__(256) void k_apply_A(Geo g, const v2<SI> *in, v2<SO> *out, const v2<G> *links,
+                                                 const v2<G> *clov)
+{
+    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.V) return;
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    const long Vd = g.Vd;
+    cx<T> acc[12];
+    {
+        cx<T> s[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = ld<T, SI>(in, ((long)d * 12 + k) * Vd + loc);
+        clover_apply<T, G>(clov, (long)d * 36 * Vd + loc, Vd, s, acc);
+    }
+    a_hops<0, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
+    a_hops<1, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
+    a_hops<2, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
+    a_hops<3, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
+#pragma unroll
+    for (int k = 0; k < 12; k++) st<T, SO>(out, ((long)d * 12 + k) * Vd + loc, acc[k]);
+}
+
+hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
+                   hipStream_t s)
+{
+    unsigned nb = nblocks(g.V, 256);
+    if (prec == P64)
+        hipLaunchKernelGGL((k_apply_A<double, double, double, double, 9>), nb, 256, 0, s, g, (const double2 *)in,
+                           (double2 *)out, (const double2 *)links, (const double2 *)clov);
+    else if (prec == P32)
+        hipLaunchKernelGGL((k_apply_A<float, float, float, float, 6>), nb, 256, 0, s, g, (const float2 *)in,
+                           (float2 *)out, (const float2 *)links, (const float2 *)clov);
+    else
+        hipLaunchKernelGGL((k_apply_A<float, half_t, half_t, half_t, 6>), nb, 256, 0, s, g, (const half2_t *)in,
+                           (half2_t *)out, (const half2_t *)links, (const half2_t *)clov);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// FP64 linear algebra (deterministic two-stage reductions)
+// ===========================================================================
+
+constexpr int BS = 256;
+
+template <int N> __device__ __forceinline__ void block_reduce_store(double (&v)[N], double2 *dst_pairs)
+{
+    // wave64 butterfly, then the waves of the block through LDS in fixed order
+    __shared__ double red[BS / 64][N];
+#pragma unroll
+    for (int q = 0; q < N; q++)
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; q++) red[w][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q + 1 < N + 1; q += 2) {
+            double a = 0, b = 0;
+            for (int k = 0; k < BS / 64; k++) {
+                a += red[k][q];
+                if (q + 1 < N) b += red[k][q + 1];
+            }
+            dst_pairs[q / 2] = make_double2(a, b);
+        }
+    }
+}
+
+// stage 2: result[j] = sum over blocks of partial[b][j], j < m pairs
+__global__ void k_finish(const double2 *partial, int m, double2 *result)
+{
+    __shared__ double2 red[BS];
+    for (int j = 0; j < m; j++) {
+        double2 s = make_double2(0, 0);
+        for (int b = threadIdx.x; b < BLAS_NBLK; b += BS) {
+            double2 v = partial[(long)b * 32 + j];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = BS / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                red[threadIdx.x].x += red[threadIdx.x + o].x;
+                red[threadIdx.x].y += red[threadIdx.x + o].y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) result[j] = red[0];
+        __syncthreads();
+    }
+}
+
+template <int K> __global__ __launch_bounds__(BS) void k_multidot(const double2 *W, long ldw, const double2 *v, long n, double2 *partial)
+{
+    double acc[2 * K];
+#pragma unroll
+    for (int q = 0; q < 2 * K; q++) acc[q] = 0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 b = v[i];
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            double2 a = W[j * ldw + i];
+            acc[2 * j] += a.x * b.x + a.y * b.y;
+            acc[2 * j + 1] += a.x * b.y - a.y * b.x;
+        }
+    }
+    block_reduce_store<2 * K>(acc, partial + (long)blockIdx.x * 32);
+}
+
+template <int K> static void launch_multidot(const double2 *W, long ldw, const double2 *v, long n, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_multidot<K>, BLAS_NBLK, BS, 0, s, W, ldw, v, n, partial);
+}
+
+hipError_t Blas::init()
+{
+    hipError_t e = hipMalloc(&partial, sizeof(double2) * BLAS_NBLK * 32);
+    if (e == hipSuccess) e = hipMalloc(&result, sizeof(double2) * 32);
+    if (e == hipSuccess) e = hipMalloc(&coef, sizeof(double2) * 32);
+    return e;
+}
+
+void Blas::release()
+{
+    if (partial) (void)hipFree(partial);
+    if (result) (void)hipFree(result);
+    if (coef) (void)hipFree(coef);
+    partial = result = coef = nullptr;
+}
+
+hipError_t multidot(Blas &B, const double2 *W, long ldw, int k, const double2 *v, long n, hipStream_t s)
+{
+    switch (k) {
+#define MD(K) case K: launch_multidot<K>(W, ldw, v, n, B.partial, s); break;
+        MD(1) MD(2) MD(3) MD(4) MD(5) MD(6) MD(7) MD(8) MD(9) MD(10) MD(11) MD(12) MD(13) MD(14) MD(15) MD(16)
+#undef MD
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, k, B.result);
+    return hipGetLastError();
+}
+
+template <int K>
+__global__ __launch_bounds__(BS) void k_cgs_update(double2 *w, const double2 *W, long ldw, const double2 *coef, const double2 *r,
+                                                   long n, double2 *partial)
+{
+    double2 c[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; j++) c[j] = coef[j];
+    double acc[4] = {0, 0, 0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 x = w[i];
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            double2 a = W[j * ldw + i];
+            x.x -= c[j].x * a.x - c[j].y * a.y;
+            x.y -= c[j].x * a.y + c[j].y * a.x;
+        }
+        w[i] = x;
+        double2 b = r[i];
+        acc[0] += x.x * x.x + x.y * x.y;
+        acc[2] += x.x * b.x + x.y * b.y;
+        acc[3] += x.x * b.y - x.y * b.x;
+    }
+    block_reduce_store<4>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, const double2 *r, long n, hipStream_t s)
+{
+    switch (k) {
+#define CU(K) case K: hipLaunchKernelGGL(k_cgs_update<K>, BLAS_NBLK, BS, 0, s, w, W, ldw, B.coef, r, n, B.partial); break;
+        CU(0) CU(1) CU(2) CU(3) CU(4) CU(5) CU(6) CU(7) CU(8) CU(9) CU(10) CU(11) CU(12) CU(13) CU(14) CU(15) CU(16)
+#undef CU
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 2, B.result);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BS) void k_normalize_update(double2 *w, double inv_b, double2 *r, double2 c, long n, double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 x = w[i];
+        x.x *= inv_b;
+        x.y *= inv_b;
+        w[i] = x;
+        double2 y = r[i];
+        y.x -= c.x * x.x - c.y * x.y;
+        y.y -= c.x * x.y + c.y * x.x;
+        r[i] = y;
+        acc[0] += y.x * y.x + y.y * y.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_normalize_update, BLAS_NBLK, BS, 0, s, w, inv_b, r, c, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    return hipGetLastError();
+}
+
+template <int K> __global__ __launch_bounds__(BS) void k_axpy_multi(double2 *x, const double2 *Z, long ldz, const double2 *coef, long n)
+{
+    double2 c[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) c[j] = coef[j];
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 y = x[i];
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            double2 a = Z[j * ldz + i];
+            y.x += c[j].x * a.x - c[j].y * a.y;
+            y.y += c[j].x * a.y + c[j].y * a.x;
+        }
+        x[i] = y;
+    }
+}
+
+hipError_t axpy_multi(Blas &B, double2 *x, const double2 *Z, long ldz, int k, long n, hipStream_t s)
+{
+    switch (k) {
+#define AX(K) case K: hipLaunchKernelGGL(k_axpy_multi<K>, BLAS_NBLK, BS, 0, s, x, Z, ldz, B.coef, n); break;
+        AX(1) AX(2) AX(3) AX(4) AX(5) AX(6) AX(7) AX(8) AX(9) AX(10) AX(11) AX(12) AX(13) AX(14) AX(15) AX(16)
+#undef AX
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BS) void k_residual(const double2 *b, double2 *r, long n, double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 y = b[i], a = r[i];
+        y.x -= a.x;
+        y.y -= a.y;
+        r[i] = y;
+        acc[0] += y.x * y.x + y.y * y.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual, BLAS_NBLK, BS, 0, s, b, r, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BS) void k_norm2(const double2 *v, long n, double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+        double2 y = v[i];
+        acc[0] += y.x * y.x + y.y * y.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm2, BLAS_NBLK, BS, 0, s, v, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(double2 *v, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        v[i] = make_double2(0, 0);
+}
+
+hipError_t zero(double2 *v, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, 2048, 256, 0, s, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace dd

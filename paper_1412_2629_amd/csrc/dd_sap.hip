@@ -1,0 +1,496 @@
+// One half-sweep of the Schwarz alternating procedure (multiplicative
+// Schwarz, Sec. II-D and the algorithm of Table I): every domain of one colour
+// solves D_Omega delta = rho_Omega approximately and adds delta to the
+// solution.  One workgroup per domain, one thread per site; the spinors the
+// block solve exchanges between sites live in LDS for the whole solve.
+//
+// Residual bookkeeping.  After a domain's block solve its residual is known
+// exactly: the MR residual on the even sites and zero on the odd sites
+// (Sec. II-D, Eq. 5).  Between two solves of a domain only its neighbours
+// (the other colour) change the solution, by their own delta, so the domain
+// next sees
+//     rho = stored block residual - R delta_neighbours .
+// Each domain therefore stores, after its solve, its block residual and the
+// boundary half-spinors of its delta (the terms of R that its neighbours
+// need: (1 - gamma_mu) delta on its -mu face, U_mu^dagger (1 + gamma_mu) delta
+// on its +mu face), and gathers its neighbours' at the start of its next
+// solve.  This is the paper's packed boundary buffers (Sec. III-A) with the
+// gather done by the reading domain, so no two workgroups write the same
+// address and no atomics are needed.
+#include <hip/hip_runtime.h>
+
+#include "dd_device.h"
+#include "dd_internal.h"
+
+namespace dd {
+
+template <int BX, int BY, int BZ, int BT> struct Shape {
+    static constexpr int VD = BX * BY * BZ * BT;
+    static constexpr int VH = VD / 2;
+    static constexpr int B[4] = {BX, BY, BZ, BT};
+    static constexpr int FS[4] = {VD / BX, VD / BY, VD / BZ, VD / BT};
+    static constexpr int FTOT = 2 * (VD / BX + VD / BY + VD / BZ + VD / BT);
+    static_assert(BX % 2 == 0 && BY % 2 == 0 && BZ % 2 == 0 && BT % 2 == 0, "domain extents must be even");
+
+    // face f = 2*mu + side (side 0: l_mu = 0, side 1: l_mu = B_mu - 1)
+    static constexpr int foff(int f)
+    {
+        int o = 0;
+        for (int q = 0; q < f; q++) o += FS[q >> 1];
+        return o;
+    }
+    __device__ static void coords(int loc, int l[4])
+    {
+        int p = loc >= VH;
+        int h = loc - p * VH;
+        int xh = h % (BX / 2);
+        int row = h / (BX / 2);
+        l[1] = row % BY;
+        row /= BY;
+        l[2] = row % BZ;
+        l[3] = row / BZ;
+        l[0] = 2 * xh + ((p + l[1] + l[2] + l[3]) & 1);
+    }
+    // index within the half-lattice of the site's own parity
+    __device__ static int half_index(const int l[4]) { return (l[0] + BX * (l[1] + BY * (l[2] + BZ * l[3]))) >> 1; }
+    template <int MU> __device__ static int face_index(const int l[4])
+    {
+        if constexpr (MU == 0) return l[1] + BY * (l[2] + BZ * l[3]);
+        else if constexpr (MU == 1) return l[0] + BX * (l[2] + BZ * l[3]);
+        else if constexpr (MU == 2) return l[0] + BX * (l[1] + BY * l[3]);
+        else return l[0] + BX * (l[1] + BY * l[2]);
+    }
+};
+
+// ---- block reductions over all VD threads (deterministic order) -----------
+
+template <int VD, typename T, int N> __device__ __forceinline__ void block_sum(T (&v)[N], T *red)
+{
+    if constexpr (VD >= 64) {
+        constexpr int NW = VD / 64;
+#pragma unroll
+        for (int q = 0; q < N; q++)
+            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < N; q++) red[q * NW + w] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < N; q++) {
+            T s = 0;
+            for (int k = 0; k < NW; k++) s += red[q * NW + k];
+            v[q] = s;
+        }
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int q = 0; q < N; q++) red[q * VD + threadIdx.x] = v[q];
+        __syncthreads();
+        for (int o = VD / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o)
+#pragma unroll
+                for (int q = 0; q < N; q++) red[q * VD + threadIdx.x] += red[q * VD + threadIdx.x + o];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < N; q++) v[q] = red[q * VD];
+        __syncthreads();
+    }
+}
+
+template <int VD, typename T> __device__ __forceinline__ T block_max(T v, T *red)
+{
+    if constexpr (VD >= 64) {
+        constexpr int NW = VD / 64;
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        T m = red[0];
+        for (int k = 1; k < NW; k++) m = fmax(m, red[k]);
+        __syncthreads();
+        return m;
+    } else {
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = VD / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+            __syncthreads();
+        }
+        T m = red[0];
+        __syncthreads();
+        return m;
+    }
+}
+
+// smallest power of two >= m (m > 0), 1 for m == 0
+template <typename T> __device__ __forceinline__ T pow2_ceil(T m)
+{
+    if (!(m > T(0))) return T(1);
+    int e;
+    T f = frexp(m, &e);   // m = f * 2^e, f in [0.5, 1)
+    (void)f;
+    return ldexp(T(1), e);
+}
+
+template <typename T> __device__ __forceinline__ T maxabs12(const cx<T> a[12])
+{
+    T m = 0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) m = fmax(m, fmax(fabs(a[k].r), fabs(a[k].i)));
+    return m;
+}
+
+// ---- in-domain hopping terms from an LDS half-lattice spinor --------------
+//
+// acc += sum over in-domain neighbours of (1 - gamma_mu) U_mu(x) v(x+mu) and
+// (1 + gamma_mu) U_mu(x-mu)^dagger v(x-mu); the -1/2 of Eq. 1 is applied by
+// the caller.  v holds the sites of the other parity.
+
+template <class Sh, int MU, typename T, typename G, int NLC>
+__device__ __forceinline__ void dom_hop(const cx<T> (*v)[Sh::VH], const int l[4], long lbase, int loc,
+                                        const v2<G> *links, cx<T> acc[12])
+{
+    constexpr int VD = Sh::VD;
+    int n[4] = {l[0], l[1], l[2], l[3]};
+    cx<T> s[12], h[6], uh[6];
+    if (l[MU] + 1 < Sh::B[MU]) {
+        n[MU] = l[MU] + 1;
+        int nh = Sh::half_index(n);
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = v[k][nh];
+        proj<MU, -1>(s, h);
+        su3<T> U = ld_link<T, G, NLC>(links, lbase + (long)MU * NLC * VD + loc, VD);
+        su3_mul(U, h, uh);
+        recon_acc<MU, -1>(acc, uh, T(1));
+    }
+    if (l[MU] > 0) {
+        n[MU] = l[MU] - 1;
+        int nh = Sh::half_index(n);
+        int nloc = (1 - (loc >= Sh::VH)) * Sh::VH + nh;
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = v[k][nh];
+        proj<MU, +1>(s, h);
+        su3<T> U = ld_link<T, G, NLC>(links, lbase + (long)MU * NLC * VD + nloc, VD);
+        su3_dag_mul(U, h, uh);
+        recon_acc<MU, +1>(acc, uh, T(1));
+    }
+}
+
+template <class Sh, typename T, typename G, int NLC>
+__device__ __forceinline__ void dom_hops(const cx<T> (*v)[Sh::VH], const int l[4], long lbase, int loc,
+                                         const v2<G> *links, cx<T> acc[12])
+{
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = czero<T>();
+    dom_hop<Sh, 0, T, G, NLC>(v, l, lbase, loc, links, acc);
+    dom_hop<Sh, 1, T, G, NLC>(v, l, lbase, loc, links, acc);
+    dom_hop<Sh, 2, T, G, NLC>(v, l, lbase, loc, links, acc);
+    dom_hop<Sh, 3, T, G, NLC>(v, l, lbase, loc, links, acc);
+}
+
+// ---- boundary terms --------------------------------------------------------
+
+template <class Sh> __device__ __forceinline__ long face_base(int d, int f) { return ((long)d * Sh::FTOT + Sh::foff(f)) * 6; }
+
+// rho += 1/2 phi * (the hop from the neighbouring domain across each face)
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC, bool SCALED>
+__device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], int d, const int l[4], int loc,
+                                            cx<T> rho[12])
+{
+    constexpr int VD = Sh::VD;
+    const v2<SS> *face = (const v2<SS> *)a.face;
+    int Dn[4] = {D[0], D[1], D[2], D[3]};
+    cx<T> h[6];
+    if (l[MU] == 0) {
+        // backward hop from x - mu, in the -mu neighbour's +mu face
+        bool wrap = D[MU] == 0;
+        Dn[MU] = wrap ? a.g.n[MU] - 1 : D[MU] - 1;
+        int dn = Dn[0] + a.g.n[0] * (Dn[1] + a.g.n[1] * (Dn[2] + a.g.n[2] * Dn[3]));
+        T sc = SCALED ? T(a.face_scale[dn]) : T(1);
+        long fb = face_base<Sh>(dn, 2 * MU + 1);
+        int fi = Sh::template face_index<MU>(l);
+#pragma unroll
+        for (int k = 0; k < 6; k++) h[k] = scal(sc, ld<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi));
+        recon_acc<MU, +1>(rho, h, T(wrap ? 0.5 * a.g.bc[MU] : 0.5));
+    } else if (l[MU] == Sh::B[MU] - 1) {
+        // forward hop from x + mu, in the +mu neighbour's -mu face
+        bool wrap = D[MU] == a.g.n[MU] - 1;
+        Dn[MU] = wrap ? 0 : D[MU] + 1;
+        int dn = Dn[0] + a.g.n[0] * (Dn[1] + a.g.n[1] * (Dn[2] + a.g.n[2] * Dn[3]));
+        T sc = SCALED ? T(a.face_scale[dn]) : T(1);
+        long fb = face_base<Sh>(dn, 2 * MU);
+        int fi = Sh::template face_index<MU>(l);
+#pragma unroll
+        for (int k = 0; k < 6; k++) h[k] = scal(sc, ld<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi));
+        cx<T> uh[6];
+        su3<T> U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        su3_mul(U, h, uh);
+        recon_acc<MU, -1>(rho, uh, T(wrap ? 0.5 * a.g.bc[MU] : 0.5));
+    }
+}
+
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC>
+__device__ __forceinline__ void write_face(const SapArgs &a, int d, const int l[4], int loc, const cx<T> delta[12],
+                                           T inv_sc)
+{
+    constexpr int VD = Sh::VD;
+    v2<SS> *face = (v2<SS> *)a.face;
+    cx<T> h[6];
+    if (l[MU] == 0) {
+        proj<MU, -1>(delta, h);
+        long fb = face_base<Sh>(d, 2 * MU);
+        int fi = Sh::template face_index<MU>(l);
+#pragma unroll
+        for (int k = 0; k < 6; k++) st<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi, scal(inv_sc, h[k]));
+    } else if (l[MU] == Sh::B[MU] - 1) {
+        cx<T> uh[6];
+        proj<MU, +1>(delta, h);
+        su3<T> U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        su3_dag_mul(U, h, uh);
+        long fb = face_base<Sh>(d, 2 * MU + 1);
+        int fi = Sh::template face_index<MU>(l);
+#pragma unroll
+        for (int k = 0; k < 6; k++) st<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi, scal(inv_sc, uh[k]));
+    }
+}
+
+// ---- the half-sweep kernel --------------------------------------------------
+//
+// One workgroup per domain, one thread per (even site, odd site) pair: thread
+// t owns the even site with half-lattice index t and the odd site with
+// half-lattice index t, so in every phase of the block solve (which works on
+// one parity at a time) all threads are busy.  The MR residual r of the even
+// site stays in registers; the MR solution x, the odd-site right-hand side
+// rho_o and the exchanged half-lattice spinors live in LDS.
+//
+// T: arithmetic; SS: storage of the block residual and the boundary terms;
+// PS: storage of the solution accumulator; G: storage of links and clover;
+// RHO_LDS: keep rho_o in LDS (else in a per-domain global buffer, used when
+// four FP64 half-lattice spinors would not fit in LDS).
+
+template <class Sh, typename T, typename SS, typename G, int NLC, bool SCALED>
+__device__ __forceinline__ void stage_site(const SapArgs &a, const int D[4], int d, const int l[4], int loc,
+                                           cx<T> rho[12])
+{
+    constexpr int VD = Sh::VD, VH = Sh::VH;
+    const long sidx = (long)d * 12 * VD + loc;
+    if (a.first) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) rho[k] = ld<T, double>(a.eta, sidx + (long)k * VD);
+    } else if (loc < VH) {
+        T sc = SCALED ? T(a.res_scale[d]) : T(1);
+        const v2<SS> *res = (const v2<SS> *)a.res;
+#pragma unroll
+        for (int k = 0; k < 12; k++) rho[k] = scal(sc, ld<T, SS>(res, ((long)d * 12 + k) * VH + loc));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) rho[k] = czero<T>();
+    }
+    if (a.faces_in) {
+        gather_face<Sh, 0, T, SS, G, NLC, SCALED>(a, D, d, l, loc, rho);
+        gather_face<Sh, 1, T, SS, G, NLC, SCALED>(a, D, d, l, loc, rho);
+        gather_face<Sh, 2, T, SS, G, NLC, SCALED>(a, D, d, l, loc, rho);
+        gather_face<Sh, 3, T, SS, G, NLC, SCALED>(a, D, d, l, loc, rho);
+    }
+}
+
+template <class Sh, typename T, typename SS, typename PS, typename G, int NLC>
+__device__ __forceinline__ void write_site(const SapArgs &a, int d, const int l[4], int loc, const cx<T> delta[12],
+                                           T inv_face_sc)
+{
+    constexpr int VD = Sh::VD;
+    const long sidx = (long)d * 12 * VD + loc;
+    const v2<PS> *psi_in = (const v2<PS> *)a.psi;
+    v2<PS> *psi_out = (v2<PS> *)a.psi;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        cx<T> ps = a.first ? delta[k] : ld<T, PS>(psi_in, sidx + (long)k * VD) + delta[k];
+        if (a.last) st<T, double>(a.out, sidx + (long)k * VD, ps);
+        else st<T, PS>(psi_out, sidx + (long)k * VD, ps);
+    }
+    if (a.faces_out) {
+        write_face<Sh, 0, T, SS, G, NLC>(a, d, l, loc, delta, inv_face_sc);
+        write_face<Sh, 1, T, SS, G, NLC>(a, d, l, loc, delta, inv_face_sc);
+        write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, delta, inv_face_sc);
+        write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, delta, inv_face_sc);
+    }
+}
+
+template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool RHO_LDS>
+__global__ __launch_bounds__(Sh::VH) void k_sap_sweep(SapArgs a)
+{
+    constexpr int VD = Sh::VD, VH = Sh::VH;
+    __shared__ cx<T> she[12][VH];                                  // even-site spinor being hopped
+    __shared__ cx<T> sho[12][VH];                                  // odd-site spinor being hopped
+    __shared__ cx<T> shx[12][VH];                                  // MR solution on the even sites
+    __shared__ cx<T> shr[RHO_LDS ? 12 : 1][RHO_LDS ? VH : 1];      // rho on the odd sites
+    __shared__ T red[VH >= 64 ? 3 * (VH / 64) : 3 * VH];
+
+    const int d = a.dom[blockIdx.x];
+    const int t = threadIdx.x;
+    const int loc_e = t, loc_o = VH + t;
+    int le[4], lo[4];
+    Sh::coords(loc_e, le);
+    Sh::coords(loc_o, lo);
+    int D[4];
+    {
+        int r = d;
+        D[0] = r % a.g.n[0]; r /= a.g.n[0];
+        D[1] = r % a.g.n[1]; r /= a.g.n[1];
+        D[2] = r % a.g.n[2];
+        D[3] = r / a.g.n[2];
+    }
+    const v2<G> *links = (const v2<G> *)a.links;
+    const v2<G> *cs = (const v2<G> *)a.cs;
+    const long lbase = (long)d * 4 * NLC * VD;
+    const long cbase = (long)d * 36 * VD;
+    v2<T> *rho_g = (v2<T> *)a.rho_tmp;
+
+    cx<T> r[12], P[12];
+
+    // ---- staging (Sec. II-D: the residual restricted to the domain)
+    {
+        cx<T> ro[12];
+        stage_site<Sh, T, SS, G, NLC, SCALED>(a, D, d, lo, loc_o, ro);
+        // odd part of the preparation: C_o^-1 rho_o
+        clover_apply<T, G>(cs, cbase + loc_o, VD, ro, P);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            sho[k][t] = P[k];
+            if constexpr (RHO_LDS) shr[k][t] = ro[k];
+            else st<T, T>(rho_g, ((long)d * 12 + k) * VH + t, ro[k]);
+            shx[k][t] = czero<T>();
+        }
+    }
+    stage_site<Sh, T, SS, G, NLC, SCALED>(a, D, d, le, loc_e, r);
+    __syncthreads();
+    // r = rho_e - D_eo C_o^-1 rho_o  (D_eo = -1/2 hops)
+    dom_hops<Sh, T, G, NLC>(sho, le, lbase, loc_e, links, P);
+#pragma unroll
+    for (int k = 0; k < 12; k++) r[k] = r[k] + scal(T(0.5), P[k]);
+
+    // ---- minimal residual on the Schur complement C_e - D_eo C_o^-1 D_oe
+    for (int it = 0; it < a.n_mr; it++) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) she[k][t] = r[k];
+        __syncthreads();
+        {
+            cx<T> q[12];
+            dom_hops<Sh, T, G, NLC>(she, lo, lbase, loc_o, links, q);
+#pragma unroll
+            for (int k = 0; k < 12; k++) q[k] = scal(T(-0.5), q[k]);   // D_oe r
+            clover_apply<T, G>(cs, cbase + loc_o, VD, q, P);           // C_o^-1 D_oe r
+#pragma unroll
+            for (int k = 0; k < 12; k++) sho[k][t] = P[k];
+        }
+        __syncthreads();
+        T dots[3] = {0, 0, 0};
+        {
+            cx<T> q[12];
+            dom_hops<Sh, T, G, NLC>(sho, le, lbase, loc_e, links, q);
+            clover_apply<T, G>(cs, cbase + loc_e, VD, r, P);           // C_e r
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                P[k] = P[k] + scal(T(0.5), q[k]);                      // p = C_e r - D_eo C_o^-1 D_oe r
+                dots[0] += P[k].r * r[k].r + P[k].i * r[k].i;
+                dots[1] += P[k].r * r[k].i - P[k].i * r[k].r;
+                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+            }
+        }
+        block_sum<VH, T, 3>(dots, red);
+        const cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            shx[k][t] = shx[k][t] + alpha * r[k];
+            r[k] = r[k] - alpha * P[k];
+        }
+    }
+    __syncthreads();
+
+    // ---- odd sites: delta_o = C_o^-1 (rho_o - D_oe x)
+    {
+        cx<T> q[12];
+        dom_hops<Sh, T, G, NLC>(shx, lo, lbase, loc_o, links, q);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            cx<T> ro;
+            if constexpr (RHO_LDS) ro = shr[k][t];
+            else ro = ld<T, T>(rho_g, ((long)d * 12 + k) * VH + t);
+            q[k] = ro + scal(T(0.5), q[k]);
+        }
+        clover_apply<T, G>(cs, cbase + loc_o, VD, q, P);               // P = delta_o
+    }
+
+    // ---- epilogue: psi += delta, stored residual, boundary terms
+    T face_sc = T(1);
+    if (a.res_out) {
+        T sc = T(1);
+        if constexpr (SCALED) {
+            sc = pow2_ceil(block_max<VH, T>(maxabs12(r), red));
+            if (t == 0) a.res_scale[d] = (float)sc;
+        }
+        v2<SS> *res = (v2<SS> *)a.res;
+        T inv = T(1) / sc;
+#pragma unroll
+        for (int k = 0; k < 12; k++) st<T, SS>(res, ((long)d * 12 + k) * VH + t, scal(inv, r[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) r[k] = shx[k][t];                    // r <- delta_e
+    if (a.faces_out) {
+        if constexpr (SCALED) {
+            face_sc = T(8) * pow2_ceil(block_max<VH, T>(fmax(maxabs12(r), maxabs12(P)), red));
+            if (t == 0) a.face_scale[d] = (float)face_sc;
+        }
+    }
+    write_site<Sh, T, SS, PS, G, NLC>(a, d, lo, loc_o, P, T(1) / face_sc);
+    write_site<Sh, T, SS, PS, G, NLC>(a, d, le, loc_e, r, T(1) / face_sc);
+}
+
+// ---- dispatch ---------------------------------------------------------------
+
+template <class Sh> static hipError_t launch_shape(const SapArgs &a, int prec, hipStream_t s)
+{
+    dim3 grid(a.ndom), block(Sh::VH);
+    if (prec == P64)
+        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), grid, block, 0, s, a);
+    else if (prec == P32)
+        hipLaunchKernelGGL((k_sap_sweep<Sh, float, float, float, float, 6, false, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sap_sweep<Sh, float, half_t, float, half_t, 6, true, true>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+static int shape_id(const int b[4])
+{
+    if (b[0] == 2 && b[1] == 2 && b[2] == 2 && b[3] == 2) return 0;
+    if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 1;
+    if (b[0] == 8 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 2;
+    return -1;
+}
+
+bool sap_shape_supported(const int b[4]) { return shape_id(b) >= 0; }
+
+// FP64 block solves are built for 2^4 domains only: on larger domains the
+// FP64 instantiation spills registers to scratch memory, and that variant is
+// switched off until it is shown correct on the device.
+bool sap_prec_supported(const int b[4], int prec) { return shape_id(b) >= 0 && (prec != P64 || shape_id(b) == 0); }
+
+long sap_face_sites(const int b[4])
+{
+    long Vd = (long)b[0] * b[1] * b[2] * b[3];
+    return 2 * (Vd / b[0] + Vd / b[1] + Vd / b[2] + Vd / b[3]);
+}
+
+hipError_t sap_sweep(const SapArgs &a, int prec, hipStream_t s)
+{
+    if (!sap_prec_supported(a.g.b, prec)) return hipErrorInvalidValue;
+    switch (shape_id(a.g.b)) {
+        case 0: return launch_shape<Shape<2, 2, 2, 2>>(a, prec, s);
+        case 1: return launch_shape<Shape<4, 4, 4, 4>>(a, prec, s);
+        case 2: return launch_shape<Shape<8, 4, 4, 4>>(a, prec, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dd

@@ -1,0 +1,152 @@
+"""Python binding of the ddqcd C-ABI (include/ddqcd.h).
+
+Argument marshalling only: torch tensors on the GPU become device pointers,
+the current torch stream becomes the hipStream_t.  Every step of the solver
+runs in libddqcd.so; there is no fallback.  Fields are complex128 tensors in
+the canonical layouts: gauge (V, 4, 3, 3), spinor (V, 4, 3) or (nrhs, V, 4, 3).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddqcd.so")
+
+OK, ERR_ARG, ERR_GEOMETRY, ERR_STATE, ERR_DEVICE, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINITE = range(8)
+FP64, FP32, FP16 = 0, 1, 2
+PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
+
+EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_solver", "ddqcd_load_gauge",
+           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_last_error", "ddqcd_status_string"]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("t_total_ms", ctypes.c_double), ("t_sap_ms", ctypes.c_double),
+                ("t_A_ms", ctypes.c_double), ("t_gs_ms", ctypes.c_double), ("t_other_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DDQCDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1412_2629_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.ddqcd_create.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), d, d, ctypes.POINTER(d), ctypes.POINTER(vp)]
+        L.ddqcd_destroy.argtypes = [vp]
+        L.ddqcd_set_sap.argtypes = [vp, i, i, i]
+        L.ddqcd_set_solver.argtypes = [vp, i, d, i]
+        L.ddqcd_load_gauge.argtypes = [vp, vp, vp]
+        L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
+        L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
+        L.ddqcd_solve.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
+        L.ddqcd_last_error.argtypes = [vp]
+        L.ddqcd_last_error.restype = ctypes.c_char_p
+        L.ddqcd_status_string.argtypes = [i]
+        L.ddqcd_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("ddqcd_last_error", "ddqcd_status_string"):
+                getattr(L, name).restype = i
+        _LIB = L
+    return _LIB
+
+
+def status_string(st):
+    return lib().ddqcd_status_string(st).decode()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous complex128 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One lattice: geometry, operator parameters, gauge field and solver state."""
+
+    def __init__(self, lattice, domain, kappa, csw, boundary=(1.0, 1.0, 1.0, -1.0)):
+        self.lattice = tuple(int(v) for v in lattice)
+        self.domain = tuple(int(v) for v in domain)
+        self.V = self.lattice[0] * self.lattice[1] * self.lattice[2] * self.lattice[3]
+        h = ctypes.c_void_p()
+        st = lib().ddqcd_create((ctypes.c_int * 4)(*self.lattice), (ctypes.c_int * 4)(*self.domain),
+                                ctypes.c_double(kappa), ctypes.c_double(csw),
+                                (ctypes.c_double * 4)(*[float(b) for b in boundary]), ctypes.byref(h))
+        if st != OK:
+            raise DDQCDError(st, f"ddqcd_create({self.lattice}, {self.domain}) failed: {status_string(st)}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ddqcd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != OK:
+            raise DDQCDError(st, f"{what}: {status_string(st)}: {lib().ddqcd_last_error(self._h).decode()}")
+
+    def set_sap(self, n_cycles=16, n_mr=5, prec="f32"):
+        self._check(lib().ddqcd_set_sap(self._h, n_cycles, n_mr, PREC[prec]), "set_sap")
+
+    def set_solver(self, restart=16, tol=1e-10, max_cycles=64):
+        self._check(lib().ddqcd_set_solver(self._h, restart, ctypes.c_double(tol), max_cycles), "set_solver")
+
+    def load_gauge(self, U):
+        assert U.shape == (self.V, 4, 3, 3), U.shape
+        self._check(lib().ddqcd_load_gauge(self._h, _ptr(U, "U"), _stream()), "load_gauge")
+
+    def _nrhs(self, t):
+        if t.shape == (self.V, 4, 3):
+            return 1
+        assert t.dim() == 4 and t.shape[1:] == (self.V, 4, 3), t.shape
+        return t.shape[0]
+
+    def apply_D(self, psi, prec="f64", out=None):
+        import torch
+        out = torch.empty_like(psi) if out is None else out
+        self._check(lib().ddqcd_apply_D(self._h, _ptr(out, "out"), _ptr(psi, "in"), self._nrhs(psi), PREC[prec],
+                                        _stream()), "apply_D")
+        return out
+
+    def sap(self, eta, out=None):
+        import torch
+        out = torch.empty_like(eta) if out is None else out
+        self._check(lib().ddqcd_sap(self._h, _ptr(out, "out"), _ptr(eta, "in"), self._nrhs(eta), _stream()), "sap")
+        return out
+
+    def solve(self, b, x0=None, check=True):
+        """Returns (x, [info dicts], status)."""
+        import torch
+        nrhs = self._nrhs(b)
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        infos = (Info * nrhs)()
+        st = lib().ddqcd_solve(self._h, _ptr(x, "x"), _ptr(b, "b"), nrhs, 0 if x0 is None else 1, infos, _stream())
+        if check and st not in (OK, ERR_NOT_CONVERGED):
+            self._check(st, "solve")
+        return x, [i.as_dict() for i in infos], st

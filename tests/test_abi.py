@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports every entry point of include/ddqcd.h;
+host-side validation paths (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_2629_amd import ddqcd
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ddqcd.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddqcd_[A-Za-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_north_star_calls():
+    names = declared()
+    for n in ["ddqcd_create", "ddqcd_load_gauge", "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ddqcd.lib()
+    for n in declared():
+        assert hasattr(L, n), n
+    assert set(declared()) == set(ddqcd.EXPORTS)
+
+
+def _create(L=(8, 8, 8, 8), b=(4, 4, 4, 4), kappa=0.12, csw=1.0, bc=(1, 1, 1, -1)):
+    h = ctypes.c_void_p()
+    st = ddqcd.lib().ddqcd_create((ctypes.c_int * 4)(*L), (ctypes.c_int * 4)(*b), kappa, csw,
+                                  (ctypes.c_double * 4)(*bc), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("L,b", [((8, 8, 8, 8), (8, 4, 4, 4)),      # one domain in x
+                                 ((12, 8, 8, 8), (4, 4, 4, 4)),     # three domains in x
+                                 ((8, 8, 8, 8), (3, 4, 4, 4)),      # odd extent
+                                 ((8, 8, 8, 10), (4, 4, 4, 5)),     # odd extent
+                                 ((16, 16, 16, 16), (4, 4, 8, 4))])  # no compiled block-solve shape
+def test_create_rejects_geometry(L, b):
+    st, h = _create(L, b)
+    assert st == ddqcd.ERR_GEOMETRY and not h.value
+
+
+@pytest.mark.parametrize("kw", [dict(kappa=0.0), dict(kappa=-0.1), dict(kappa=float("nan")), dict(csw=float("inf")),
+                                dict(bc=(1, 1, 1, 0.5)), dict(bc=(1, 1, 2, -1))])
+def test_create_rejects_arguments(kw):
+    st, h = _create(**kw)
+    assert st == ddqcd.ERR_ARG and not h.value
+
+
+def test_create_settings_and_state_errors():
+    st, h = _create()
+    assert st == ddqcd.OK and h.value
+    L = ddqcd.lib()
+    try:
+        assert L.ddqcd_set_sap(h, 0, 5, 1) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 0, 1) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 5, 7) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16) == ddqcd.OK
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP64) == ddqcd.ERR_GEOMETRY   # FP64 only on 2^4 domains
+        assert b"2x2x2x2" in L.ddqcd_last_error(h)
+        assert L.ddqcd_set_solver(h, 0, 1e-10, 10) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_solver(h, 17, 1e-10, 10) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_solver(h, 16, 0.0, 10) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_solver(h, 16, 1e-10, 0) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_solver(h, 8, 1e-10, 10) == ddqcd.OK
+        dummy = ctypes.c_void_p(4096)
+        dummy2 = ctypes.c_void_p(8192)
+        # no gauge field loaded yet: rejected before any device work
+        assert L.ddqcd_apply_D(h, dummy, dummy2, 1, 0, None) == ddqcd.ERR_STATE
+        assert L.ddqcd_sap(h, dummy, dummy2, 1, None) == ddqcd.ERR_STATE
+        assert L.ddqcd_solve(h, dummy, dummy2, 1, 0, None, None) == ddqcd.ERR_STATE
+        assert b"load_gauge" in L.ddqcd_last_error(h)
+        # argument errors
+        assert L.ddqcd_apply_D(h, dummy, dummy, 1, 0, None) == ddqcd.ERR_ARG      # aliasing
+        assert L.ddqcd_apply_D(h, dummy, dummy2, 0, 0, None) == ddqcd.ERR_ARG     # nrhs
+        assert L.ddqcd_apply_D(h, dummy, dummy2, 1, 5, None) == ddqcd.ERR_ARG     # precision
+        assert L.ddqcd_load_gauge(h, None, None) == ddqcd.ERR_ARG
+    finally:
+        assert L.ddqcd_destroy(h) == ddqcd.OK
+    assert L.ddqcd_destroy(None) == ddqcd.OK
+
+
+def test_status_strings():
+    assert ddqcd.status_string(ddqcd.ERR_NOT_CONVERGED) == "DDQCD_ERR_NOT_CONVERGED"
+    assert ddqcd.status_string(99) == "unknown status"

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Tolerances (normwise relative errors):
+  operator A:  1e-13 (FP64), 1e-6 (FP32), 5e-3 (FP16 storage)
+  SAP output:  1e-12 (FP64); FP32 and FP16-storage bounds are derived from
+               the unit roundoff in the tests below
+  solve:       true residual |b - A x|/|b| <= 1e-10 with the oracle's A,
+               |x - x_oracle| / |x_oracle| <= 1e-8 (oracle solved to 1e-12)
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import BC, FP64_SAP_SKIP, SMALL, Case, dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+A_TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_2629_amd import ddqcd
+    ddqcd.lib()
+
+
+@pytest.mark.parametrize("case", SMALL, ids=repr)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_apply_D(case, prec, oracle):
+    psi = case.source()
+    want = oracle.apply_A(case.L, BC, case.U, case.C, psi)
+    ctx = case.context()
+    got = host(ctx.apply_D(dev(psi), prec))
+    err = rel(got, want)
+    print(f"{case} {prec} operator error {err:.3e}")
+    assert err <= A_TOL[prec]
+
+
+def test_apply_D_batched_rhs(oracle):
+    case = SMALL[2]
+    ctx = case.context()
+    psis = np.stack([case.source(7), case.source(8), case.source(9)])
+    got = host(ctx.apply_D(dev(psis), "f64"))
+    for k in range(3):
+        assert rel(got[k], oracle.apply_A(case.L, BC, case.U, case.C, psis[k])) <= 1e-13
+
+
+@pytest.mark.parametrize("case", SMALL, ids=repr)
+def test_sap_fp64(case, oracle):
+    if not case.fp64_sap:
+        pytest.skip(FP64_SAP_SKIP)
+    eta = case.source(5)
+    want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
+    ctx = case.context("f64")
+    got = host(ctx.sap(dev(eta)))
+    err = rel(got, want)
+    print(f"{case} SAP fp64 error {err:.3e}")
+    assert err <= 1e-12
+
+
+# Low-precision SAP against the FP64 oracle.  Every stored quantity is
+# rounded once per half-sweep with unit roundoff u (2^-24 for FP32, 2^-11
+# for FP16 storage), and a block solve damps an input perturbation (its
+# output error is at most a few times its input error), so the output error
+# stays within C * u * n_cycles with C = 10 (a bound with margin, not a fit).
+SAP_TOL = {"f32": 10 * 2.0 ** -24, "f16": 10 * 2.0 ** -11}
+
+
+@pytest.mark.parametrize("case", SMALL, ids=repr)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_sap_low_precision(case, prec, oracle):
+    eta = case.source(5)
+    want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
+    ctx = case.context(prec)
+    got = host(ctx.sap(dev(eta)))
+    err = rel(got, want)
+    print(f"{case} SAP {prec} error {err:.3e} (bound {SAP_TOL[prec] * case.n_cycles:.2e})")
+    assert err <= SAP_TOL[prec] * case.n_cycles
+
+
+@pytest.mark.parametrize("case", SMALL[:3], ids=repr)
+def test_sap_homogeneous(case):
+    eta = case.source(6)
+    ctx = case.context("f64" if case.fp64_sap else "f32")
+    s = 0.3 + 1.7j
+    m1 = host(ctx.sap(dev(eta)))
+    m2 = host(ctx.sap(dev(s * eta)))
+    assert rel(m2, s * m1) < (1e-13 if case.fp64_sap else 1e-5)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=repr)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_solve(case, prec, oracle):
+    if prec == "f64" and not case.fp64_sap:
+        pytest.skip(FP64_SAP_SKIP)
+    f = case.source(3)
+    x_or, st, steps, rr = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                      n_mr=case.n_mr, restart=16, tol=1e-12)
+    assert st == 0
+    ctx = case.context(prec)
+    ctx.set_solver(16, 1e-10, 64)
+    x, info, status = ctx.solve(dev(f))
+    x = host(x)
+    true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+    err = rel(x, x_or)
+    print(f"{case} {prec}: steps {info[0]['iters']} (oracle fp64 {steps}), true residual {true_res:.2e}, "
+          f"solution error {err:.2e}")
+    assert status == 0 and info[0]["converged"] == 1
+    assert true_res <= 1e-10
+    assert abs(info[0]["rel_residual"] - true_res) <= 1e-12
+    assert err <= 1e-8
+
+
+def test_solve_fp64_matches_oracle_iterates(oracle):
+    """The FP64 path runs the same algorithm: same number of FGCR steps."""
+    case = SMALL[0]
+    f = case.source(4)
+    _, st, steps, rr = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                   n_mr=case.n_mr, restart=16, tol=1e-10)
+    ctx = case.context("f64")
+    x, info, status = ctx.solve(dev(f))
+    assert status == 0 and info[0]["iters"] == steps
+
+
+def test_solve_multi_rhs_and_guess(oracle):
+    case = SMALL[2]
+    ctx = case.context("f32")
+    fs = np.stack([case.source(21), case.source(22)])
+    x, info, status = ctx.solve(dev(fs))
+    assert status == 0 and len(info) == 2
+    for k in range(2):
+        assert rel(oracle.apply_A(case.L, BC, case.U, case.C, host(x)[k]), fs[k]) <= 1e-10
+    # restart from the converged solution: no further steps
+    x2, info2, status2 = ctx.solve(dev(fs), x0=x)
+    assert status2 == 0 and all(i["iters"] == 0 for i in info2)
+
+
+def test_fp64_sap_switched_off_on_large_domains():
+    from paper_1412_2629_amd import ddqcd
+    ctx = SMALL[2].context()
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ctx.set_sap(4, 5, "f64")
+    assert e.value.status == ddqcd.ERR_GEOMETRY
+
+
+def test_solve_edge_cases():
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[0]
+    ctx = case.context("f64")
+    z = np.zeros((case.V, 4, 3), dtype=np.complex128)
+    x, info, st = ctx.solve(dev(z))
+    assert st == 0 and np.abs(host(x)).max() == 0 and info[0]["iters"] == 0
+    ctx.set_solver(1, 1e-10, 1)
+    x, info, st = ctx.solve(dev(case.source(1)))
+    assert st == ddqcd.ERR_NOT_CONVERGED and info[0]["iters"] == 1 and 0 < info[0]["rel_residual"] < 1
+    ctx.set_solver(16, 1e-10, 64)
+    bad = case.source(2)
+    bad[3, 1, 2] = np.nan
+    x, info, st = ctx.solve(dev(bad), check=False)
+    assert st == ddqcd.ERR_NONFINITE
+    U = case.U.copy()
+    U[5, 2, 1, 1] = np.inf
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ctx.load_gauge(dev(U))
+    assert e.value.status == ddqcd.ERR_NONFINITE
+
+
+def test_two_contexts_independent(oracle):
+    a, b = SMALL[0], SMALL[1]
+    ca, cb = a.context("f64"), b.context("f64")
+    pa, pb = a.source(31), b.source(32)
+    ga = host(ca.apply_D(dev(pa)))
+    gb = host(cb.apply_D(dev(pb)))
+    assert rel(ga, oracle.apply_A(a.L, BC, a.U, a.C, pa)) <= 1e-13
+    assert rel(gb, oracle.apply_A(b.L, BC, b.U, b.C, pb)) <= 1e-13
