@@ -34,6 +34,9 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner comparison solve")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (a known-size kernel for "
+                         "calibrating profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the lattice is solved whole on a single "
@@ -64,6 +67,14 @@ def main():
             raise RuntimeError(f"solve did not converge: {info}")
         return x, info[0]
 
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del a, b
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         solve(w.prec)
