@@ -447,17 +447,227 @@ __global__ __launch_bounds__(Sh::VH) void k_sap_sweep(SapArgs a)
     write_site<Sh, T, SS, PS, G, NLC>(a, d, le, loc_e, r, T(1) / face_sc);
 }
 
+// ---- the LDS-resident half-sweep kernel (FP32 arithmetic) -----------------
+//
+// One workgroup per domain, one thread per site.  At the start of the block
+// solve the domain's links are staged once into LDS and each thread loads its
+// own site's clover block (C on even sites, C^-1 on odd sites) into
+// registers, so the MR steps read no global memory at all: the hopping terms
+// take the neighbour spinor and the link from LDS, the site terms from
+// registers.  x and r of the even sites and rho/delta of the odd sites stay in
+// the registers of the site's own thread.
+
+template <typename T, typename G>
+__device__ __forceinline__ void clover_block_reg(const v2<G> *c, const cx<T> in[6], cx<T> out[6])
+{
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        out[2 * q] = scal(static_cast<T>(c[q].x), in[2 * q]);
+        out[2 * q + 1] = scal(static_cast<T>(c[q].y), in[2 * q + 1]);
+    }
+#pragma unroll
+    for (int i = 1; i < 6; i++)
+#pragma unroll
+        for (int j = 0; j < i; j++) {
+            v2<G> mv = c[3 + tri_index(i, j)];
+            cx<T> m = {static_cast<T>(mv.x), static_cast<T>(mv.y)};
+            out[i] = out[i] + m * in[j];
+            out[j] = out[j] + cmulc(m, in[i]);
+        }
+}
+
+template <typename T, typename G>
+__device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12], cx<T> out[12])
+{
+    clover_block_reg<T, G>(cl, in, out);
+    clover_block_reg<T, G>(cl + 18, in + 6, out + 6);
+}
+
+template <class Sh, typename SS, typename G, bool SCALED>
+__global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
+{
+    using T = float;
+    constexpr int VD = Sh::VD, VH = Sh::VH, NLC = 6;
+    __shared__ v2<G> slink[4 * NLC * VD];   // [mu][6][VD]: rows 0-1 of U_mu(x)
+    __shared__ cx<T> she[12][VH];
+    __shared__ cx<T> sho[12][VH];
+    __shared__ T red[VD >= 64 ? 3 * (VD / 64) : 3 * VD];
+
+    const int d = a.dom[blockIdx.x];
+    const int loc = threadIdx.x;
+    const int par = loc >= VH;
+    const int hi = loc - par * VH;
+    int l[4];
+    Sh::coords(loc, l);
+    int D[4];
+    {
+        int r = d;
+        D[0] = r % a.g.n[0]; r /= a.g.n[0];
+        D[1] = r % a.g.n[1]; r /= a.g.n[1];
+        D[2] = r % a.g.n[2];
+        D[3] = r / a.g.n[2];
+    }
+    const v2<G> *glinks = (const v2<G> *)a.links;
+    const v2<G> *cs = (const v2<G> *)a.cs;
+    const long sbase = (long)d * 12 * VD + loc;
+
+    // ---- stage the links into LDS, the site's clover block into registers
+    {
+        const long lb = (long)d * 4 * NLC * VD + loc;
+#pragma unroll
+        for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = glinks[lb + (long)q * VD];
+    }
+    v2<G> cl[36];
+#pragma unroll
+    for (int q = 0; q < 36; q++) cl[q] = cs[((long)d * 36 + q) * VD + loc];
+
+    // A: even sites x (MR solution), odd sites rho_o then delta_o; B: even sites r
+    cx<T> A[12], B[12], P[12];
+    if (a.first) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
+    } else if (par == 0) {
+        T sc = SCALED ? T(a.res_scale[d]) : T(1);
+        const v2<SS> *res = (const v2<SS> *)a.res;
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = scal(sc, ld<T, SS>(res, ((long)d * 12 + k) * VH + hi));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = czero<T>();
+    }
+    if (a.faces_in) {
+        gather_face<Sh, 0, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
+        gather_face<Sh, 1, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
+        gather_face<Sh, 2, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
+        gather_face<Sh, 3, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
+    }
+
+    // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0
+    if (par == 1) {
+        clover_reg<T, G>(cl, A, P);
+#pragma unroll
+        for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
+    }
+    __syncthreads();   // also publishes slink
+    if (par == 0) {
+        dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, P);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            B[k] = A[k] + scal(T(0.5), P[k]);
+            A[k] = czero<T>();
+        }
+    }
+
+    // ---- minimal residual on the Schur complement
+    for (int it = 0; it < a.n_mr; it++) {
+        if constexpr (sizeof(v2<G>) == 4) {
+            // keep the clover block in its 16-bit storage form: stops the
+            // compiler from hoisting its widening out of the loop, which would
+            // double the registers it occupies
+#pragma unroll
+            for (int q = 0; q < 36; q++) asm volatile("" : "+v"(cl[q]));
+        }
+        if (par == 0)
+#pragma unroll
+            for (int k = 0; k < 12; k++) she[k][hi] = B[k];
+        __syncthreads();
+        if (par == 1) {
+            cx<T> t[12];
+            dom_hops<Sh, T, G, NLC>(she, l, 0, loc, slink, t);
+#pragma unroll
+            for (int k = 0; k < 12; k++) t[k] = scal(T(-0.5), t[k]);   // D_oe r
+            clover_reg<T, G>(cl, t, P);                                // C_o^-1 D_oe r
+#pragma unroll
+            for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
+        }
+        __syncthreads();
+        T dots[3] = {0, 0, 0};
+        if (par == 0) {
+            cx<T> t[12];
+            dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, t);
+            clover_reg<T, G>(cl, B, P);                                // C_e r
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                P[k] = P[k] + scal(T(0.5), t[k]);
+                dots[0] += P[k].r * B[k].r + P[k].i * B[k].i;
+                dots[1] += P[k].r * B[k].i - P[k].i * B[k].r;
+                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+            }
+        }
+        block_sum<VD, T, 3>(dots, red);
+        if (par == 0) {
+            cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                A[k] = A[k] + alpha * B[k];
+                B[k] = B[k] - alpha * P[k];
+            }
+        }
+    }
+
+    // ---- odd sites: delta_o = C_o^-1 (rho_o - D_oe x)
+    if (par == 0)
+#pragma unroll
+        for (int k = 0; k < 12; k++) she[k][hi] = A[k];
+    __syncthreads();
+    if (par == 1) {
+        cx<T> t[12];
+        dom_hops<Sh, T, G, NLC>(she, l, 0, loc, slink, t);
+#pragma unroll
+        for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
+        clover_reg<T, G>(cl, t, A);
+    }
+
+    // ---- epilogue
+    {
+        const v2<float> *psi_in = (const v2<float> *)a.psi;
+        v2<float> *psi_out = (v2<float> *)a.psi;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            cx<T> ps = a.first ? A[k] : ld<T, float>(psi_in, sbase + (long)k * VD) + A[k];
+            if (a.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
+            else st<T, float>(psi_out, sbase + (long)k * VD, ps);
+        }
+    }
+    if (a.res_out) {
+        T sc = T(1);
+        if constexpr (SCALED) {
+            sc = pow2_ceil(block_max<VD, T>(par == 0 ? maxabs12(B) : T(0), red));
+            if (loc == 0) a.res_scale[d] = (float)sc;
+        }
+        if (par == 0) {
+            v2<SS> *res = (v2<SS> *)a.res;
+            T inv = T(1) / sc;
+#pragma unroll
+            for (int k = 0; k < 12; k++) st<T, SS>(res, ((long)d * 12 + k) * VH + hi, scal(inv, B[k]));
+        }
+    }
+    if (a.faces_out) {
+        T sc = T(1);
+        if constexpr (SCALED) {
+            sc = T(8) * pow2_ceil(block_max<VD, T>(maxabs12(A), red));
+            if (loc == 0) a.face_scale[d] = (float)sc;
+        }
+        T inv = T(1) / sc;
+        write_face<Sh, 0, T, SS, G, NLC>(a, d, l, loc, A, inv);
+        write_face<Sh, 1, T, SS, G, NLC>(a, d, l, loc, A, inv);
+        write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, A, inv);
+        write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, A, inv);
+    }
+}
+
 // ---- dispatch ---------------------------------------------------------------
 
 template <class Sh> static hipError_t launch_shape(const SapArgs &a, int prec, hipStream_t s)
 {
-    dim3 grid(a.ndom), block(Sh::VH);
+    dim3 grid(a.ndom);
     if (prec == P64)
-        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), grid, dim3(Sh::VH), 0,
+                           s, a);
     else if (prec == P32)
-        hipLaunchKernelGGL((k_sap_sweep<Sh, float, float, float, float, 6, false, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, false>), grid, dim3(Sh::VD), 0, s, a);
     else
-        hipLaunchKernelGGL((k_sap_sweep<Sh, float, half_t, float, half_t, 6, true, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_sap_lds<Sh, half_t, half_t, true>), grid, dim3(Sh::VD), 0, s, a);
     return hipGetLastError();
 }
 
