@@ -64,6 +64,8 @@ typedef enum {
 
 typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2 } ddqcd_prec;
 
+typedef enum { DDQCD_SCHED_SWEEPS = 0, DDQCD_SCHED_QUEUE = 1 } ddqcd_schedule;
+
 typedef struct {
     int converged;        /* 1 if |b - A x| / |b| <= tol */
     int iters;            /* FGCR steps (= preconditioner applications) */
@@ -96,6 +98,14 @@ int ddqcd_destroy(ddqcd_t ctx);
  * per-domain scales, FP32 arithmetic, FP32 solution accumulator).  FP64 is
  * available for 2x2x2x2 domains only (DDQCD_ERR_GEOMETRY otherwise). */
 int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec);
+
+/* How the block solves of one preconditioner call are scheduled.
+ * DDQCD_SCHED_SWEEPS (the default, and the only one available) launches one
+ * kernel per half-sweep: all domains of one colour at once, Sec. IV-B2's
+ * n_domain.  DDQCD_SCHED_QUEUE, one persistent kernel taking (cycle, domain)
+ * tasks from a work queue with per-domain epoch counters so that consecutive
+ * half-sweeps overlap, is switched off: selecting it returns DDQCD_ERR_ARG. */
+int ddqcd_set_schedule(ddqcd_t ctx, int schedule);
 
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the
  * true relative residual |b - A x|/|b| (Sec. IV-C1), max_cycles >= 1. */

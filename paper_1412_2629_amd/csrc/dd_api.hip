@@ -20,6 +20,10 @@ struct ddqcd_ctx {
     double kappa = 0, csw = 0;
     int n_cycles = 16, n_mr = 5, sap_prec = DDQCD_FP32;
     int restart = 16, max_cycles = 64;
+    int schedule = DDQCD_SCHED_SWEEPS;
+    int n_cu = 0;
+    int epoch_base = 0;
+    std::vector<int> order_host;
     double tol = 1e-10;
     std::string err;
     std::vector<int> dom_host[2];
@@ -29,6 +33,7 @@ struct ddqcd_ctx {
     // device memory (owned)
     int *d_dom[2] = {nullptr, nullptr};
     int *d_flag = nullptr;
+    int *d_epoch = nullptr, *d_counter = nullptr, *d_qerr = nullptr, *d_order = nullptr;
     double2 *U64 = nullptr;      // [d][mu][9][Vd]
     void *U32 = nullptr, *U16 = nullptr;   // [d][mu][6][Vd]
     double2 *C64 = nullptr;      // [d][36][Vd]
@@ -157,6 +162,32 @@ int run_sap(ddqcd_t c, const double2 *eta, double2 *out, hipStream_t s)
     a.rho_tmp = c->rho_tmp;
     a.links = links_for(c, prec);
     a.cs = schur_for(c, prec);
+    if (c->schedule == DDQCD_SCHED_QUEUE && prec != DDQCD_FP64) {
+        QueueArgs q{};
+        q.epoch = c->d_epoch;
+        q.counter = c->d_counter;
+        q.error = c->d_qerr;
+        q.base = c->epoch_base;
+        q.n_cycles = c->n_cycles;
+        q.nd = c->g.nd;
+        q.nblack = (int)c->dom_host[0].size();
+        q.order = c->d_order;
+        HIPCHK(c, sap_queue(a, q, prec, c->n_cu, s));
+        int qerr = 0;
+        HIPCHK(c, hipMemcpyAsync(&qerr, c->d_qerr, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (qerr) {
+            HIPCHK(c, queue_reset_epochs(c->d_epoch, c->g.nd, c->d_qerr, s));
+            c->epoch_base = 0;
+            return fail(c, DDQCD_ERR_DEVICE, "SAP work queue: a dependency wait exceeded its limit");
+        }
+        c->epoch_base += c->n_cycles;
+        if (c->epoch_base > (1 << 30)) {
+            HIPCHK(c, queue_reset_epochs(c->d_epoch, c->g.nd, c->d_qerr, s));
+            c->epoch_base = 0;
+        }
+        return DDQCD_OK;
+    }
     for (int cyc = 0; cyc < c->n_cycles; cyc++)
         for (int col = 0; col < 2; col++) {
             a.dom = c->d_dom[col];
@@ -422,6 +453,8 @@ int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double
         }
         c->dom_host[s & 1].push_back(d);
     }
+    c->order_host = c->dom_host[0];
+    c->order_host.insert(c->order_host.end(), c->dom_host[1].begin(), c->dom_host[1].end());
     *out = c;
     return DDQCD_OK;
 }
@@ -445,6 +478,17 @@ int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec)
     c->n_cycles = n_cycles;
     c->n_mr = n_mr;
     c->sap_prec = prec;
+    return DDQCD_OK;
+}
+
+int ddqcd_set_schedule(ddqcd_t c, int schedule)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (schedule != DDQCD_SCHED_SWEEPS && schedule != DDQCD_SCHED_QUEUE) return fail(c, DDQCD_ERR_ARG, "bad schedule");
+    if (schedule == DDQCD_SCHED_QUEUE)
+        return fail(c, DDQCD_ERR_ARG, "the work-queue schedule is switched off: it stalled on the device and its cause "
+                                      "is not established");
+    c->schedule = schedule;
     return DDQCD_OK;
 }
 
@@ -477,6 +521,14 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
                                 hipMemcpyHostToDevice));
         }
         if ((e = alloc(c, &c->d_flag, sizeof(int)))) return e;
+        if ((e = alloc(c, &c->d_epoch, sizeof(int) * g.nd))) return e;
+        if ((e = alloc(c, &c->d_counter, sizeof(int)))) return e;
+        if ((e = alloc(c, &c->d_qerr, sizeof(int)))) return e;
+        if ((e = alloc(c, &c->d_order, sizeof(int) * g.nd))) return e;
+        HIPCHK(c, hipMemcpy(c->d_order, c->order_host.data(), sizeof(int) * g.nd, hipMemcpyHostToDevice));
+        HIPCHK(c, queue_reset_epochs(c->d_epoch, g.nd, c->d_qerr, s));
+        c->epoch_base = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
         if ((e = alloc(c, &c->U64, V * 4 * 9 * 16))) return e;
         if ((e = dev_alloc(c, &c->U32, V * 4 * 6 * 8))) return e;
         if ((e = dev_alloc(c, &c->U16, V * 4 * 6 * 4))) return e;

@@ -483,8 +483,17 @@ __device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12
     clover_block_reg<T, G>(cl + 18, in + 6, out + 6);
 }
 
+// what one visit of a domain reads and writes
+struct Visit {
+    int first;      // first visit in this preconditioner call: residual is eta
+    int faces_in;   // add the neighbours' boundary terms
+    int last;       // last visit: write psi to the FP64 output
+    int faces_out;  // write this domain's boundary terms
+    int res_out;    // store the block residual
+};
+
 template <class Sh, typename SS, typename G, bool SCALED>
-__global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
+__device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
 {
     using T = float;
     constexpr int VD = Sh::VD, VH = Sh::VH, NLC = 6;
@@ -493,7 +502,6 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
     __shared__ cx<T> sho[12][VH];
     __shared__ T red[VD >= 64 ? 3 * (VD / 64) : 3 * VD];
 
-    const int d = a.dom[blockIdx.x];
     const int loc = threadIdx.x;
     const int par = loc >= VH;
     const int hi = loc - par * VH;
@@ -521,9 +529,9 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
 #pragma unroll
     for (int q = 0; q < 36; q++) cl[q] = cs[((long)d * 36 + q) * VD + loc];
 
-    // A: even sites x (MR solution), odd sites rho_o then delta_o; B: even sites r
-    cx<T> A[12], B[12], P[12];
-    if (a.first) {
+    // A: even sites x (MR solution), odd sites rho_o then delta_o
+    cx<T> A[12], P[12];
+    if (f.first) {
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
     } else if (par == 0) {
@@ -535,7 +543,7 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = czero<T>();
     }
-    if (a.faces_in) {
+    if (f.faces_in) {
         gather_face<Sh, 0, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
         gather_face<Sh, 1, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
         gather_face<Sh, 2, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
@@ -549,16 +557,19 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
         for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
     }
     __syncthreads();   // also publishes slink
+    // the even-site MR residual r lives in its own slot of she for the whole
+    // solve (fewer live registers); x stays in the registers of A
     if (par == 0) {
         dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, P);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            B[k] = A[k] + scal(T(0.5), P[k]);
+            she[k][hi] = A[k] + scal(T(0.5), P[k]);
             A[k] = czero<T>();
         }
     }
 
     // ---- minimal residual on the Schur complement
+#pragma unroll 1
     for (int it = 0; it < a.n_mr; it++) {
         if constexpr (sizeof(v2<G>) == 4) {
             // keep the clover block in its 16-bit storage form: stops the
@@ -567,9 +578,6 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
 #pragma unroll
             for (int q = 0; q < 36; q++) asm volatile("" : "+v"(cl[q]));
         }
-        if (par == 0)
-#pragma unroll
-            for (int k = 0; k < 12; k++) she[k][hi] = B[k];
         __syncthreads();
         if (par == 1) {
             cx<T> t[12];
@@ -583,14 +591,16 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
         __syncthreads();
         T dots[3] = {0, 0, 0};
         if (par == 0) {
-            cx<T> t[12];
+            cx<T> t[12], rr[12];
             dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, t);
-            clover_reg<T, G>(cl, B, P);                                // C_e r
+#pragma unroll
+            for (int k = 0; k < 12; k++) rr[k] = she[k][hi];
+            clover_reg<T, G>(cl, rr, P);                               // C_e r
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 P[k] = P[k] + scal(T(0.5), t[k]);
-                dots[0] += P[k].r * B[k].r + P[k].i * B[k].i;
-                dots[1] += P[k].r * B[k].i - P[k].i * B[k].r;
+                dots[0] += P[k].r * rr[k].r + P[k].i * rr[k].i;
+                dots[1] += P[k].r * rr[k].i - P[k].i * rr[k].r;
                 dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
             }
         }
@@ -599,20 +609,22 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
             cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
 #pragma unroll
             for (int k = 0; k < 12; k++) {
-                A[k] = A[k] + alpha * B[k];
-                B[k] = B[k] - alpha * P[k];
+                cx<T> rk = she[k][hi];
+                A[k] = A[k] + alpha * rk;
+                she[k][hi] = rk - alpha * P[k];
             }
         }
     }
 
-    // ---- odd sites: delta_o = C_o^-1 (rho_o - D_oe x)
+    // ---- odd sites: delta_o = C_o^-1 (rho_o - D_oe x); x goes through sho
+    // (free since the last reduction), she keeps r for the epilogue
     if (par == 0)
 #pragma unroll
-        for (int k = 0; k < 12; k++) she[k][hi] = A[k];
+        for (int k = 0; k < 12; k++) sho[k][hi] = A[k];
     __syncthreads();
     if (par == 1) {
         cx<T> t[12];
-        dom_hops<Sh, T, G, NLC>(she, l, 0, loc, slink, t);
+        dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
         clover_reg<T, G>(cl, t, A);
@@ -624,25 +636,28 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
         v2<float> *psi_out = (v2<float> *)a.psi;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            cx<T> ps = a.first ? A[k] : ld<T, float>(psi_in, sbase + (long)k * VD) + A[k];
-            if (a.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
+            cx<T> ps = f.first ? A[k] : ld<T, float>(psi_in, sbase + (long)k * VD) + A[k];
+            if (f.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
             else st<T, float>(psi_out, sbase + (long)k * VD, ps);
         }
     }
-    if (a.res_out) {
+    if (f.res_out) {
+        cx<T> rr[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) rr[k] = par == 0 ? she[k][hi] : czero<T>();
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = pow2_ceil(block_max<VD, T>(par == 0 ? maxabs12(B) : T(0), red));
+            sc = pow2_ceil(block_max<VD, T>(maxabs12(rr), red));
             if (loc == 0) a.res_scale[d] = (float)sc;
         }
         if (par == 0) {
             v2<SS> *res = (v2<SS> *)a.res;
             T inv = T(1) / sc;
 #pragma unroll
-            for (int k = 0; k < 12; k++) st<T, SS>(res, ((long)d * 12 + k) * VH + hi, scal(inv, B[k]));
+            for (int k = 0; k < 12; k++) st<T, SS>(res, ((long)d * 12 + k) * VH + hi, scal(inv, rr[k]));
         }
     }
-    if (a.faces_out) {
+    if (f.faces_out) {
         T sc = T(1);
         if constexpr (SCALED) {
             sc = T(8) * pow2_ceil(block_max<VD, T>(maxabs12(A), red));
@@ -654,6 +669,106 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
         write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, A, inv);
         write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, A, inv);
     }
+}
+
+
+template <class Sh, typename SS, typename G, bool SCALED>
+__global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
+{
+    lds_block_solve<Sh, SS, G, SCALED>(a, a.dom[blockIdx.x], Visit{a.first, a.faces_in, a.last, a.faces_out, a.res_out});
+}
+
+// ---- persistent work-queue kernel -------------------------------------------
+//
+// All block solves of one preconditioner call in one launch.  Tasks are the
+// pairs (cycle s, domain d), dequeued in the order: cycle 0 black domains,
+// cycle 0 white domains, cycle 1 black, ...  A task may start when the
+// neighbouring domains have finished the visit it depends on (black at cycle
+// s: the white neighbours' cycle s-1; white at cycle s: the black neighbours'
+// cycle s), read from per-domain epoch counters.  Every task waited on has a
+// smaller queue index, so it has already been dequeued by a running
+// workgroup: the queue drains without any assumption on how many workgroups
+// are resident, and white domains of cycle s overlap black domains of cycle
+// s+1 wherever their neighbours are done.  A wait that exceeds a spin limit
+// raises the error flag, and every later wait then gives up at once, so the
+// grid always drains.
+
+// Polling uses relaxed system-scope loads: they read memory past the L2 of
+// this XCD without invalidating it.  (Acquire loads would invalidate the L2
+// on every poll; with most workgroups polling, that continuous invalidation
+// starves the workgroups whose results are being waited for.)  One acquire
+// fence follows a successful wait; the counter, the epochs and the error flag
+// are system-scope atomics, so they are coherent across the XCDs' L2 caches.
+constexpr int QUEUE_SPIN_LIMIT = 1 << 19;
+
+__device__ __forceinline__ bool wait_epoch(const QueueArgs &q, int nb, int need)
+{
+    int spins = 0;
+    while (__hip_atomic_load(&q.epoch[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
+        if (__hip_atomic_load(q.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) return false;
+        if (++spins > QUEUE_SPIN_LIMIT) {
+            __hip_atomic_fetch_or(q.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(32);
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool wait_neighbours(const QueueArgs &q, const Geo &g, int d, int need)
+{
+    int D[4];
+    {
+        int r = d;
+        D[0] = r % g.n[0]; r /= g.n[0];
+        D[1] = r % g.n[1]; r /= g.n[1];
+        D[2] = r % g.n[2];
+        D[3] = r / g.n[2];
+    }
+    for (int mu = 0; mu < 4; mu++)
+        for (int step = -1; step <= 1; step += 2) {
+            int E[4] = {D[0], D[1], D[2], D[3]};
+            E[mu] = (E[mu] + step + g.n[mu]) % g.n[mu];
+            int nb = E[0] + g.n[0] * (E[1] + g.n[1] * (E[2] + g.n[2] * E[3]));
+            if (!wait_epoch(q, nb, need)) return false;
+        }
+    return true;
+}
+
+template <class Sh, typename SS, typename G, bool SCALED>
+__global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
+{
+    __shared__ int task_s, ok_s;
+    const int ntask = q.n_cycles * q.nd;
+    for (;;) {
+        if (threadIdx.x == 0) task_s = __hip_atomic_fetch_add(q.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __syncthreads();
+        // the task is the same for the whole workgroup: keep it in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(task_s);
+        __syncthreads();
+        if (t >= ntask) break;
+        const int s = t / q.nd, k = t - s * q.nd;
+        const int d = __builtin_amdgcn_readfirstlane(q.order[k]);
+        const int colour = k >= q.nblack;
+        if (threadIdx.x == 0) ok_s = wait_neighbours(q, a.g, d, q.base + s + colour);
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(ok_s)) continue;
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);   // system scope: see the neighbours' results
+        const int last = s == q.n_cycles - 1;
+        lds_block_solve<Sh, SS, G, SCALED>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
+        __threadfence_system();                     // this block's results reach memory ...
+        __syncthreads();
+        if (threadIdx.x == 0)                       // ... before its epoch moves on
+            __hip_atomic_store(&q.epoch[d], q.base + s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__global__ void k_queue_reset(int *counter) { *counter = 0; }
+
+__global__ void k_epoch_reset(int *epoch, int nd, int *error)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) epoch[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *error = 0;
 }
 
 // ---- dispatch ---------------------------------------------------------------
@@ -690,6 +805,39 @@ long sap_face_sites(const int b[4])
 {
     long Vd = (long)b[0] * b[1] * b[2] * b[3];
     return 2 * (Vd / b[0] + Vd / b[1] + Vd / b[2] + Vd / b[3]);
+}
+
+template <class Sh> static hipError_t launch_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, 1, 1, 0, s, q.counter);
+    int per_cu = 0;
+    hipError_t e;
+    if (prec == P32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sap_queue<Sh, float, float, false>, Sh::VD, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sap_queue<Sh, half_t, half_t, true>, Sh::VD, 0);
+    if (e != hipSuccess) return e;
+    long grid = (long)n_cu * (per_cu > 0 ? per_cu : 1);
+    long ntask = (long)q.n_cycles * q.nd;
+    if (grid > ntask) grid = ntask;
+    if (prec == P32) hipLaunchKernelGGL((k_sap_queue<Sh, float, float, false>), dim3(grid), dim3(Sh::VD), 0, s, a, q);
+    else hipLaunchKernelGGL((k_sap_queue<Sh, half_t, half_t, true>), dim3(grid), dim3(Sh::VD), 0, s, a, q);
+    return hipGetLastError();
+}
+
+hipError_t sap_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s)
+{
+    if (prec == P64 || !sap_prec_supported(a.g.b, prec)) return hipErrorInvalidValue;
+    switch (shape_id(a.g.b)) {
+        case 0: return launch_queue<Shape<2, 2, 2, 2>>(a, q, prec, n_cu, s);
+        case 1: return launch_queue<Shape<4, 4, 4, 4>>(a, q, prec, n_cu, s);
+        case 2: return launch_queue<Shape<8, 4, 4, 4>>(a, q, prec, n_cu, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t queue_reset_epochs(int *epoch, int nd, int *error, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_epoch_reset, 64, 256, 0, s, epoch, nd, error);
+    return hipGetLastError();
 }
 
 hipError_t sap_sweep(const SapArgs &a, int prec, hipStream_t s)

@@ -15,7 +15,9 @@ OK, ERR_ARG, ERR_GEOMETRY, ERR_STATE, ERR_DEVICE, ERR_NOMEM, ERR_NOT_CONVERGED, 
 FP64, FP32, FP16 = 0, 1, 2
 PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
 
-EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_solver", "ddqcd_load_gauge",
+SCHED_SWEEPS, SCHED_QUEUE = 0, 1
+
+EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_last_error", "ddqcd_status_string"]
 
 
@@ -48,6 +50,7 @@ def lib():
         L.ddqcd_destroy.argtypes = [vp]
         L.ddqcd_set_sap.argtypes = [vp, i, i, i]
         L.ddqcd_set_solver.argtypes = [vp, i, d, i]
+        L.ddqcd_set_schedule.argtypes = [vp, i]
         L.ddqcd_load_gauge.argtypes = [vp, vp, vp]
         L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
         L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
@@ -113,6 +116,11 @@ class Context:
 
     def set_sap(self, n_cycles=16, n_mr=5, prec="f32"):
         self._check(lib().ddqcd_set_sap(self._h, n_cycles, n_mr, PREC[prec]), "set_sap")
+
+    def set_schedule(self, schedule):
+        """"sweeps" (one launch per half-sweep) or "queue" (persistent work-queue kernel)."""
+        mode = {"sweeps": SCHED_SWEEPS, "queue": SCHED_QUEUE}.get(schedule, schedule)
+        self._check(lib().ddqcd_set_schedule(self._h, mode), "set_schedule")
 
     def set_solver(self, restart=16, tol=1e-10, max_cycles=64):
         self._check(lib().ddqcd_set_solver(self._h, restart, ctypes.c_double(tol), max_cycles), "set_solver")

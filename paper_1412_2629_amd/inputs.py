@@ -13,6 +13,8 @@ Canonical layouts (what the C-ABI takes):
 The paper's runs use production gauge ensembles (Sec. IV-C); those are
 replaced by these synthetic fields of the same shapes.
 """
+import os
+
 import numpy as np
 
 # Gell-Mann matrices lambda_1..lambda_8 (standard su(3) generators).
@@ -43,25 +45,31 @@ def _rng(seed):
 def _expi_hermitian(H, eps):
     """exp(i*eps*H) for a batch of Hermitian 3x3 matrices, via eigh."""
     w, v = np.linalg.eigh(H)
-    ph = np.exp(1j * eps * w)
-    return np.einsum("...ik,...k,...jk->...ij", v, ph, v.conj())
+    return (v * np.exp(1j * eps * w)[..., None, :]) @ v.conj().swapaxes(-1, -2)
 
 
-def random_gauge(L, eps, seed, chunk=1 << 18):
+def random_gauge(L, eps, seed, chunk=1 << 16):
     """U_mu(x) = exp(i*eps*H), H = sum_a w_a lambda_a / 2, w_a ~ N(0,1) i.i.d.
 
     Drawn as w of shape (Lt, Lz, Ly, Lx, 4, 8) in C order from PCG64(seed), so
     the field is a fixed function of (L, eps, seed).  Returns (V, 4, 3, 3)
-    complex128 in the canonical layout.
+    complex128 in the canonical layout.  Chunks are exponentiated in a thread
+    pool (the result does not depend on the chunking).
     """
+    from concurrent.futures import ThreadPoolExecutor
     V = volume(L)
     rng = _rng(seed)
     w = rng.standard_normal((V * 4, 8))
     U = np.empty((V * 4, 3, 3), dtype=np.complex128)
-    for a in range(0, V * 4, chunk):
+    gm = (_GM / 2).reshape(8, 9)
+
+    def work(a):
         b = min(V * 4, a + chunk)
-        H = np.einsum("na,aij->nij", w[a:b], _GM / 2)
+        H = (w[a:b] @ gm).reshape(-1, 3, 3)
         U[a:b] = _expi_hermitian(H, eps)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, V * 4, chunk)))
     return U.reshape(V, 4, 3, 3)
 
 

@@ -1,0 +1,94 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+Operator: sampled output sites (random sites plus every site of two whole
+domains) computed one by one by the oracle.  Solve: the true residual
+|b - A x|/|b| evaluated with the oracle's operator at every site, and (16^3x32)
+the solution against the oracle's own solve to 1e-12.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from paper_1412_2629_amd import configs, inputs
+from tests.gpu_cases import dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+A_TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@functools.lru_cache(maxsize=2)
+def fields(name):
+    w = configs.WORKLOADS[name]
+    print(f"[fullsize] generating {name} inputs", flush=True)
+    return w, inputs.random_gauge(w.lattice, w.eps, w.gauge_seed), inputs.gaussian_source(w.lattice, w.source_seed)
+
+
+def context(w, U):
+    from paper_1412_2629_amd import ddqcd
+    ctx = ddqcd.Context(w.lattice, w.domain, w.kappa, w.csw, w.bc)
+    ctx.load_gauge(dev(U))
+    ctx.set_sap(w.n_cycles, w.n_mr, w.prec)
+    ctx.set_solver(w.restart, w.tol, 64)
+    return ctx
+
+
+def sample_sites(w, n=3000, seed=0):
+    L, b = w.lattice, w.domain
+    rng = np.random.default_rng(seed)
+    sites = set(rng.integers(0, w.volume, size=n).tolist())
+    # two whole domains: the first one and the last one
+    for X in ([0, 0, 0, 0], [L[m] // b[m] - 1 for m in range(4)]):
+        for lt in range(b[3]):
+            for lz in range(b[2]):
+                for ly in range(b[1]):
+                    for lx in range(b[0]):
+                        x = [X[0] * b[0] + lx, X[1] * b[1] + ly, X[2] * b[2] + lz, X[3] * b[3] + lt]
+                        sites.add(x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3])))
+    return np.array(sorted(sites), dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_apply_D_sampled(name, oracle):
+    w, U, f = fields(name)
+    ctx = context(w, U)
+    sites = sample_sites(w)
+    want = oracle.apply_A_sites(w.lattice, w.bc, U, w.kappa, w.csw, f, sites)
+    fd = dev(f)
+    for prec in ("f64", "f32", "f16"):
+        got = host(ctx.apply_D(fd, prec))[sites]
+        err = rel(got, want)
+        print(f"{name} {prec}: operator error on {len(sites)} sampled sites {err:.3e}")
+        assert err <= A_TOL[prec]
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_solve_true_residual(name, oracle):
+    w, U, f = fields(name)
+    ctx = context(w, U)
+    x, info, st = ctx.solve(dev(f))
+    assert st == 0, info
+    x = host(x)
+    Ax = oracle.apply_A_sites(w.lattice, w.bc, U, w.kappa, w.csw, x, np.arange(w.volume, dtype=np.int64))
+    true_res = rel(Ax, f)
+    print(f"{name}: {info[0]['iters']} FGCR steps, true residual (oracle A) {true_res:.3e}, "
+          f"reported {info[0]['rel_residual']:.3e}")
+    assert true_res <= 1e-10
+    assert abs(true_res - info[0]["rel_residual"]) <= 1e-12
+    if name == "C2":
+        C = oracle.clover_field(w.lattice, U, w.kappa, w.csw)
+        Ci = oracle.clover_inverse(C)
+        x_or, st_or, steps, rr = oracle.fgcr(w.lattice, w.domain, w.bc, U, C, Ci, f, n_cycles=w.n_cycles,
+                                             n_mr=w.n_mr, restart=w.restart, tol=1e-12)
+        assert st_or == 0
+        err = rel(x, x_or)
+        print(f"C2: solution error vs oracle {err:.3e} (oracle {steps} steps)")
+        assert err <= 1e-8

@@ -67,17 +67,45 @@ def test_sap_fp64(case, oracle):
 # stays within C * u * n_cycles with C = 10 (a bound with margin, not a fit).
 SAP_TOL = {"f32": 10 * 2.0 ** -24, "f16": 10 * 2.0 ** -11}
 
+# The persistent work-queue kernel stalled on the device twice (first with
+# acquire polling, then with relaxed system-scope polling); its cause is not
+# established, so the library refuses that schedule and these cases stay off.
+QUEUE_SKIP = "work-queue schedule switched off in the library (stalled on the device, cause not established)"
+
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
 @pytest.mark.parametrize("prec", ["f32", "f16"])
-def test_sap_low_precision(case, prec, oracle):
+@pytest.mark.parametrize("sched", ["sweeps", "queue"])
+def test_sap_low_precision(case, prec, sched, oracle):
+    if sched == "queue":
+        pytest.skip(QUEUE_SKIP)
     eta = case.source(5)
     want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
     ctx = case.context(prec)
+    ctx.set_schedule(sched)
     got = host(ctx.sap(dev(eta)))
     err = rel(got, want)
-    print(f"{case} SAP {prec} error {err:.3e} (bound {SAP_TOL[prec] * case.n_cycles:.2e})")
+    print(f"{case} SAP {prec} {sched} error {err:.3e} (bound {SAP_TOL[prec] * case.n_cycles:.2e})")
     assert err <= SAP_TOL[prec] * case.n_cycles
+
+
+@pytest.mark.parametrize("case", SMALL[1:], ids=repr)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_queue_equals_sweeps_bitwise(case, prec):
+    """The work-queue schedule runs the same block solves on the same inputs in
+    the same arithmetic order as the per-half-sweep launches: identical bits,
+    also over repeated calls (epoch counters advance) with changing cycle counts."""
+    pytest.skip(QUEUE_SKIP)
+    eta = dev(case.source(9))
+    ctx = case.context(prec)
+    for n_cycles in (case.n_cycles, 1, 3, case.n_cycles):
+        ctx.set_sap(n_cycles, case.n_mr, prec)
+        ctx.set_schedule("sweeps")
+        a = host(ctx.sap(eta))
+        ctx.set_schedule("queue")
+        b = host(ctx.sap(eta))
+        c = host(ctx.sap(eta))
+        assert np.array_equal(a, b) and np.array_equal(b, c), n_cycles
 
 
 @pytest.mark.parametrize("case", SMALL[:3], ids=repr)
@@ -135,6 +163,15 @@ def test_solve_multi_rhs_and_guess(oracle):
     # restart from the converged solution: no further steps
     x2, info2, status2 = ctx.solve(dev(fs), x0=x)
     assert status2 == 0 and all(i["iters"] == 0 for i in info2)
+
+
+def test_queue_schedule_switched_off():
+    from paper_1412_2629_amd import ddqcd
+    ctx = SMALL[0].context("f32")
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ctx.set_schedule("queue")
+    assert e.value.status == ddqcd.ERR_ARG
+    ctx.set_schedule("sweeps")
 
 
 def test_fp64_sap_switched_off_on_large_domains():
