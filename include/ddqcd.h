@@ -136,6 +136,23 @@ int ddqcd_sap(ddqcd_t ctx, double *out, const double *in, int nrhs, void *stream
  * iterate).  b and x must not alias. */
 int ddqcd_solve(ddqcd_t ctx, double *x, const double *b, int nrhs, int x_is_guess, ddqcd_info *info, void *stream);
 
+/* Solves n independent systems A_i x_i = b_i at once: system i belongs to
+ * context ctxs[i] (a context may appear several times: its right-hand sides),
+ * and x[i], b[i] are device pointers to one spinor field each in that
+ * context's canonical layout.  The contexts may differ in lattice, domain
+ * shape, kappa, c_sw, gauge field and block-solve precision, but must share
+ * restart, tol, max_cycles and n_cycles (DDQCD_ERR_ARG otherwise).  Each half-
+ * sweep of the preconditioner is one launch per (domain shape, precision)
+ * over the domains of every system, so small lattices fill the device
+ * together; each system stops when it has converged.  The parallelism over
+ * configurations and sources is the batch dimension of Sec. IV-B2 (n_domain
+ * per half-sweep times the number of systems).  x_is_guess and info as for
+ * ddqcd_solve (info receives n records).  The return value is that of
+ * ddqcd_solve over all systems; an error names the context in its
+ * ddqcd_last_error. */
+int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double *const *b, int x_is_guess,
+                      ddqcd_info *info, void *stream);
+
 /* Text of the last error on this context (never NULL; "" if none). */
 const char *ddqcd_last_error(ddqcd_t ctx);
 

@@ -1,12 +1,21 @@
 // The C-ABI of include/ddqcd.h: context management, argument validation,
 // the preconditioner driver and the flexible GCR outer solver.
+//
+// A "system" is one right-hand side of one lattice (context).  Solves and
+// preconditioner calls work on a list of systems in lockstep: one block-solve
+// launch per colour of a half-sweep covers every system of one domain shape
+// and storage precision, and the outer solver's reductions for all systems are
+// read back with one host synchronisation per round.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -15,39 +24,69 @@
 
 using namespace dd;
 
+namespace {
+
+// work space of one right-hand side of a context
+struct Slot {
+    void *psi = nullptr, *res = nullptr, *face = nullptr, *rho_tmp = nullptr;   // block solves
+    float *res_scale = nullptr, *face_scale = nullptr;
+    double2 *x = nullptr, *r = nullptr, *b = nullptr;                            // FP64 vectors
+    double2 *Z = nullptr, *W = nullptr;                                          // FGCR basis
+    int zw_restart = 0;
+    Blas blas;
+};
+
+// Device-side description of the block solves of a list of systems: the
+// per-system argument array and, per (domain shape, precision) group and
+// colour, the list of (system, domain) work items.  Workgroup i of a launch
+// runs on XCD i mod 8; the items of one lattice domain (the right-hand sides
+// of one context) are placed on one XCD, so that domain's links and clover
+// blocks are fetched into one L2.
+struct Plan {
+    struct Group {
+        int shape = 0, prec = 0;
+        int2 *items[2] = {nullptr, nullptr};
+        int nitems[2] = {0, 0};
+    };
+    std::vector<Group> groups;
+    SapArgs *d_args = nullptr;
+    std::vector<SapArgs> h_args;
+    ~Plan()
+    {
+        (void)hipFree(d_args);
+        for (Group &G : groups)
+            for (int c = 0; c < 2; c++) (void)hipFree(G.items[c]);
+    }
+};
+
+constexpr int N_XCD = 8;
+constexpr size_t MAX_PLANS = 32;
+
+}  // namespace
+
 struct ddqcd_ctx {
     Geo g{};
     double kappa = 0, csw = 0;
     int n_cycles = 16, n_mr = 5, sap_prec = DDQCD_FP32;
     int restart = 16, max_cycles = 64;
-    int schedule = DDQCD_SCHED_SWEEPS;
-    int n_cu = 0;
-    int epoch_base = 0;
-    std::vector<int> order_host;
     double tol = 1e-10;
+    int schedule = DDQCD_SCHED_SWEEPS;
     std::string err;
-    std::vector<int> dom_host[2];
+    std::vector<int> dom_host[2];   // black (0) and white (1) domains
     bool loaded = false;
     int device = -1;
 
     // device memory (owned)
-    int *d_dom[2] = {nullptr, nullptr};
     int *d_flag = nullptr;
-    int *d_epoch = nullptr, *d_counter = nullptr, *d_qerr = nullptr, *d_order = nullptr;
-    double2 *U64 = nullptr;      // [d][mu][9][Vd]
+    double2 *U64 = nullptr;                // [d][mu][9][Vd]
     void *U32 = nullptr, *U16 = nullptr;   // [d][mu][6][Vd]
-    double2 *C64 = nullptr;      // [d][36][Vd]
+    double2 *C64 = nullptr;                // [d][36][Vd]
     void *C32 = nullptr, *C16 = nullptr;
-    double2 *Cs64 = nullptr;     // C_e / C_o^-1
+    double2 *Cs64 = nullptr;               // C_e / C_o^-1
     void *Cs32 = nullptr, *Cs16 = nullptr;
-    // spinor work space
-    double2 *t_in = nullptr, *t_out = nullptr;     // FP64 internal
-    void *t_lo_in = nullptr, *t_lo_out = nullptr;  // FP32/FP16 internal (max size)
-    void *psi = nullptr, *res = nullptr, *face = nullptr, *rho_tmp = nullptr;
-    float *res_scale = nullptr, *face_scale = nullptr;
-    double2 *x = nullptr, *r = nullptr, *b = nullptr, *Z = nullptr, *W = nullptr;
-    int zw_restart = 0;
-    Blas blas;
+    void *t_lo_in = nullptr, *t_lo_out = nullptr;   // FP32/FP16 operands of apply_D
+    std::vector<std::unique_ptr<Slot>> slots;
+    std::map<std::string, std::unique_ptr<Plan>> plans;   // batch plans led by this context
     std::vector<void *> owned;
 };
 
@@ -67,10 +106,7 @@ int fail(ddqcd_t c, int code, const std::string &msg)
                         std::string(#expr) + ": " + hipGetErrorString(_e));                                 \
     } while (0)
 
-long nsites(const Geo &g) { return g.V; }
 long ncomplex(const Geo &g) { return g.V * 12; }
-
-size_t elem_bytes(int prec) { return prec == DDQCD_FP64 ? 16 : prec == DDQCD_FP32 ? 8 : 4; }
 
 int dev_alloc(ddqcd_t c, void **p, size_t bytes)
 {
@@ -94,110 +130,179 @@ int check_device(ddqcd_t c)
     return DDQCD_OK;
 }
 
+int check_ready(ddqcd_t c, const char *what)
+{
+    if (!c->loaded) return fail(c, DDQCD_ERR_STATE, std::string(what) + " before load_gauge");
+    return check_device(c);
+}
+
 const void *links_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->U64 : prec == DDQCD_FP32 ? c->U32 : c->U16; }
 const void *clover_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->C64 : prec == DDQCD_FP32 ? c->C32 : c->C16; }
 const void *schur_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->Cs64 : prec == DDQCD_FP32 ? c->Cs32 : c->Cs16; }
 
-int ensure_spinor_tmp(ddqcd_t c)
-{
-    if (c->t_in) return DDQCD_OK;
-    size_t n = (size_t)ncomplex(c->g);
-    int e;
-    if ((e = alloc(c, &c->t_in, n * 16))) return e;
-    if ((e = alloc(c, &c->t_out, n * 16))) return e;
-    if ((e = alloc(c, &c->t_lo_in, n * 8))) return e;
-    if ((e = alloc(c, &c->t_lo_out, n * 8))) return e;
-    return DDQCD_OK;
-}
+// ---- per right-hand-side work space ----------------------------------------
 
-int ensure_sap_space(ddqcd_t c)
+int ensure_slots(ddqcd_t c, int n)
 {
-    if (c->psi) return DDQCD_OK;
     const Geo &g = c->g;
-    size_t n = (size_t)ncomplex(g);
-    int e;
-    if ((e = dev_alloc(c, &c->psi, n * 16))) return e;                    // FP64 or FP32 accumulator
-    if ((e = dev_alloc(c, &c->res, (size_t)g.nd * 12 * g.Vh * 16))) return e;
-    if ((e = dev_alloc(c, &c->rho_tmp, (size_t)g.nd * 12 * g.Vh * 16))) return e;
-    if ((e = dev_alloc(c, &c->face, (size_t)g.nd * sap_face_sites(g.b) * 6 * 16))) return e;
-    if ((e = alloc(c, &c->res_scale, (size_t)g.nd * 4))) return e;
-    if ((e = alloc(c, &c->face_scale, (size_t)g.nd * 4))) return e;
-    return DDQCD_OK;
-}
-
-int ensure_solver_space(ddqcd_t c)
-{
-    size_t n = (size_t)ncomplex(c->g);
-    int e;
-    if (!c->x) {
-        if ((e = alloc(c, &c->x, n * 16))) return e;
-        if ((e = alloc(c, &c->r, n * 16))) return e;
-        if ((e = alloc(c, &c->b, n * 16))) return e;
-    }
-    if (c->zw_restart < c->restart) {
-        // grow the basis (the old one, if any, stays owned until destroy)
-        if ((e = alloc(c, &c->Z, n * 16 * c->restart))) return e;
-        if ((e = alloc(c, &c->W, n * 16 * c->restart))) return e;
-        c->zw_restart = c->restart;
+    const size_t nc = (size_t)ncomplex(g);
+    while ((int)c->slots.size() < n) {
+        auto sl = std::make_unique<Slot>();
+        int e;
+        if ((e = dev_alloc(c, &sl->psi, nc * 16))) return e;   // FP64 or FP32 accumulator
+        if ((e = dev_alloc(c, &sl->res, (size_t)g.nd * 12 * g.Vh * 16))) return e;
+        if ((e = dev_alloc(c, &sl->rho_tmp, (size_t)g.nd * 12 * g.Vh * 16))) return e;
+        if ((e = dev_alloc(c, &sl->face, (size_t)g.nd * sap_face_sites(g.b) * 6 * 16))) return e;
+        if ((e = alloc(c, &sl->res_scale, (size_t)g.nd * 4))) return e;
+        if ((e = alloc(c, &sl->face_scale, (size_t)g.nd * 4))) return e;
+        if ((e = alloc(c, &sl->x, nc * 16))) return e;
+        if ((e = alloc(c, &sl->r, nc * 16))) return e;
+        if ((e = alloc(c, &sl->b, nc * 16))) return e;
+        if ((e = alloc(c, &sl->blas.partial, sizeof(double2) * BLAS_NBLK * 32))) return e;
+        if ((e = alloc(c, &sl->blas.result, sizeof(double2) * 32))) return e;
+        if ((e = alloc(c, &sl->blas.coef, sizeof(double2) * 32))) return e;
+        c->slots.push_back(std::move(sl));
     }
     return DDQCD_OK;
 }
 
-// psi = M eta on internal FP64 vectors
-int run_sap(ddqcd_t c, const double2 *eta, double2 *out, hipStream_t s)
+int ensure_basis(ddqcd_t c, Slot &sl)
 {
-    int e = ensure_sap_space(c);
-    if (e) return e;
-    const int prec = c->sap_prec;
-    SapArgs a{};
-    a.g = c->g;
-    a.n_mr = c->n_mr;
-    a.eta = eta;
-    a.out = out;
-    a.psi = c->psi;
-    a.res = c->res;
-    a.res_scale = c->res_scale;
-    a.face = c->face;
-    a.face_scale = c->face_scale;
-    a.rho_tmp = c->rho_tmp;
-    a.links = links_for(c, prec);
-    a.cs = schur_for(c, prec);
-    if (c->schedule == DDQCD_SCHED_QUEUE && prec != DDQCD_FP64) {
-        QueueArgs q{};
-        q.epoch = c->d_epoch;
-        q.counter = c->d_counter;
-        q.error = c->d_qerr;
-        q.base = c->epoch_base;
-        q.n_cycles = c->n_cycles;
-        q.nd = c->g.nd;
-        q.nblack = (int)c->dom_host[0].size();
-        q.order = c->d_order;
-        HIPCHK(c, sap_queue(a, q, prec, c->n_cu, s));
-        int qerr = 0;
-        HIPCHK(c, hipMemcpyAsync(&qerr, c->d_qerr, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        if (qerr) {
-            HIPCHK(c, queue_reset_epochs(c->d_epoch, c->g.nd, c->d_qerr, s));
-            c->epoch_base = 0;
-            return fail(c, DDQCD_ERR_DEVICE, "SAP work queue: a dependency wait exceeded its limit");
-        }
-        c->epoch_base += c->n_cycles;
-        if (c->epoch_base > (1 << 30)) {
-            HIPCHK(c, queue_reset_epochs(c->d_epoch, c->g.nd, c->d_qerr, s));
-            c->epoch_base = 0;
-        }
+    if (sl.zw_restart >= c->restart) return DDQCD_OK;
+    const size_t nc = (size_t)ncomplex(c->g);
+    int e;
+    // grow the basis (a smaller old one stays owned until destroy)
+    if ((e = alloc(c, &sl.Z, nc * 16 * c->restart))) return e;
+    if ((e = alloc(c, &sl.W, nc * 16 * c->restart))) return e;
+    sl.zw_restart = c->restart;
+    return DDQCD_OK;
+}
+
+// ---- systems and batch plans ------------------------------------------------
+
+struct Sys {
+    ddqcd_t c;
+    Slot *sl;
+    int slot;
+};
+
+// the plan depends on each system's context, slot, precision and geometry
+std::string plan_key(const std::vector<Sys> &sys)
+{
+    std::string k;
+    char buf[160];
+    for (const Sys &s : sys) {
+        const Geo &g = s.c->g;
+        snprintf(buf, sizeof buf, "%p:%d:%d:%d,%d,%d,%d:%d,%d,%d,%d;", (void *)s.c, s.slot, s.c->sap_prec, g.L[0],
+                 g.L[1], g.L[2], g.L[3], g.b[0], g.b[1], g.b[2], g.b[3]);
+        k += buf;
+    }
+    return k;
+}
+
+int build_plan(const std::vector<Sys> &sys, Plan *&out)
+{
+    ddqcd_t lead = sys[0].c;
+    const std::string key = plan_key(sys);
+    auto it = lead->plans.find(key);
+    if (it != lead->plans.end()) {
+        out = it->second.get();
         return DDQCD_OK;
     }
-    for (int cyc = 0; cyc < c->n_cycles; cyc++)
+    if (lead->plans.size() >= MAX_PLANS) {
+        HIPCHK(lead, hipDeviceSynchronize());   // no launch may still read an old plan
+        lead->plans.clear();
+    }
+    auto plan = std::make_unique<Plan>();
+    HIPCHK(lead, hipMalloc(&plan->d_args, sizeof(SapArgs) * sys.size()));
+    plan->h_args.resize(sys.size());
+    // group the systems by (domain shape, precision)
+    std::vector<std::pair<int, int>> gk;
+    std::vector<std::vector<int>> members;
+    for (size_t i = 0; i < sys.size(); i++) {
+        const std::pair<int, int> k{sap_shape_id(sys[i].c->g.b), sys[i].c->sap_prec};
+        size_t gi = std::find(gk.begin(), gk.end(), k) - gk.begin();
+        if (gi == gk.size()) {
+            gk.push_back(k);
+            members.emplace_back();
+        }
+        members[gi].push_back((int)i);
+    }
+    for (size_t gi = 0; gi < gk.size(); gi++) {
+        plan->groups.emplace_back();
+        Plan::Group &G = plan->groups.back();
+        G.shape = gk[gi].first;
+        G.prec = gk[gi].second;
         for (int col = 0; col < 2; col++) {
-            a.dom = c->d_dom[col];
-            a.ndom = (int)c->dom_host[col].size();
-            a.first = cyc == 0;
-            a.faces_in = !(cyc == 0 && col == 0);
-            a.last = cyc == c->n_cycles - 1;
-            a.faces_out = !(a.last && col == 1);
-            a.res_out = !a.last;
-            HIPCHK(c, sap_sweep(a, prec, s));
+            // one list per XCD; the items of one (context, domain) share a list
+            std::vector<std::vector<int2>> lane(N_XCD);
+            std::map<std::pair<ddqcd_t, int>, int> key_lane;
+            int next = 0;
+            for (int si : members[gi])
+                for (int d : sys[si].c->dom_host[col]) {
+                    const auto kd = std::make_pair(sys[si].c, d);
+                    auto f = key_lane.find(kd);
+                    int ln = f == key_lane.end() ? (key_lane[kd] = next++ % N_XCD) : f->second;
+                    lane[ln].push_back(make_int2(si, d));
+                }
+            size_t len = 0;
+            for (auto &l : lane) len = std::max(len, l.size());
+            std::vector<int2> items(len * N_XCD, make_int2(-1, -1));
+            for (int ln = 0; ln < N_XCD; ln++)
+                for (size_t j = 0; j < lane[ln].size(); j++) items[j * N_XCD + ln] = lane[ln][j];
+            while (!items.empty() && items.back().x < 0) items.pop_back();
+            G.nitems[col] = (int)items.size();
+            HIPCHK(lead, hipMalloc(&G.items[col], sizeof(int2) * std::max<size_t>(1, items.size())));
+            HIPCHK(lead, hipMemcpy(G.items[col], items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+        }
+    }
+    out = plan.get();
+    lead->plans[key] = std::move(plan);
+    return DDQCD_OK;
+}
+
+// out_i = M eta_i for the listed systems (internal FP64 vectors); systems with
+// on[i] == 0 are skipped.  All systems share the SAP cycle count.
+int run_sap(const std::vector<Sys> &sys, const std::vector<const double2 *> &eta, const std::vector<double2 *> &out,
+            const std::vector<int> &on, hipStream_t s)
+{
+    ddqcd_t lead = sys[0].c;
+    const int n_cycles = lead->n_cycles;
+    Plan *plan;
+    int e = build_plan(sys, plan);
+    if (e) return e;
+    for (size_t i = 0; i < sys.size(); i++) {
+        ddqcd_t c = sys[i].c;
+        Slot *sl = sys[i].sl;
+        SapArgs &a = plan->h_args[i];
+        a = SapArgs{};
+        a.g = c->g;
+        a.n_mr = c->n_mr;
+        a.eta = eta[i];
+        a.out = out[i];
+        a.psi = sl->psi;
+        a.res = sl->res;
+        a.res_scale = sl->res_scale;
+        a.face = sl->face;
+        a.face_scale = sl->face_scale;
+        a.rho_tmp = sl->rho_tmp;
+        a.links = links_for(c, c->sap_prec);
+        a.cs = schur_for(c, c->sap_prec);
+        a.active = on[i];
+    }
+    HIPCHK(lead, hipMemcpyAsync(plan->d_args, plan->h_args.data(), sizeof(SapArgs) * sys.size(),
+                                hipMemcpyHostToDevice, s));
+    // black domains first (colour 0), then white, n_cycles times
+    for (int cyc = 0; cyc < n_cycles; cyc++)
+        for (int col = 0; col < 2; col++) {
+            Visit v;
+            v.first = cyc == 0;
+            v.faces_in = !(cyc == 0 && col == 0);
+            v.last = cyc == n_cycles - 1;
+            v.faces_out = !(v.last && col == 1);
+            v.res_out = !v.last;
+            for (const Plan::Group &G : plan->groups)
+                HIPCHK(lead, sap_sweep_batch(plan->d_args, G.items[col], G.nitems[col], G.shape, G.prec, v, s));
         }
     return DDQCD_OK;
 }
@@ -235,157 +340,268 @@ struct Timer {
     ~Timer() { stop(); }
 };
 
-// reads result[0..m-1] of the last reduction
-int fetch(ddqcd_t c, double2 *host, int m, hipStream_t s)
+using C = std::complex<double>;
+
+// ---- flexible GCR over many systems in lockstep ------------------------------
+
+struct FgcrState {
+    double bn = 0, rel = 0;
+    int steps = 0, cycles = 0, kend = 0;
+    bool done = false;      // converged, or a zero source
+    bool in_cycle = false;  // still taking steps in the current cycle
+    int status = DDQCD_ERR_NOT_CONVERGED;
+    std::vector<C> a, cc, alpha;
+    std::vector<double> bb;
+    double2 h[32];          // results of the last reduction
+};
+
+// read back result[0..m-1] of every listed system with one wait
+int fetch_all(const std::vector<Sys> &sys, std::vector<FgcrState> &st, const std::vector<int> &which, int m,
+              hipStream_t s)
 {
-    HIPCHK(c, hipMemcpyAsync(host, c->blas.result, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    for (int i : which)
+        HIPCHK(sys[i].c, hipMemcpyAsync(st[i].h, sys[i].sl->blas.result, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(sys[0].c, hipStreamSynchronize(s));
     return DDQCD_OK;
 }
 
-int put_coef(ddqcd_t c, const std::vector<std::complex<double>> &v, hipStream_t s)
+int put_coef(const Sys &y, const std::vector<C> &v, hipStream_t s)
 {
-    static_assert(sizeof(std::complex<double>) == sizeof(double2), "layout");
-    HIPCHK(c, hipMemcpyAsync(c->blas.coef, v.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice, s));
+    static_assert(sizeof(C) == sizeof(double2), "layout");
+    if (v.empty()) return DDQCD_OK;
+    HIPCHK(y.c, hipMemcpyAsync(y.sl->blas.coef, v.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice, s));
     return DDQCD_OK;
 }
 
-// FGCR on internal FP64 vectors b -> x (x holds the guess if guess)
-int fgcr(ddqcd_t c, bool guess, ddqcd_info *info, hipStream_t s)
+// Solves A x = b for every system (x, b: the slot's internal FP64 vectors; x
+// holds a guess where guess[i]).  The timings are those of the whole batch.
+int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector<ddqcd_info> &info, hipStream_t s)
 {
-    const long n = ncomplex(c->g);
-    const int m = c->restart;
-    double2 *Z = c->Z, *W = c->W;
+    const int ns = (int)sys.size();
+    ddqcd_t lead = sys[0].c;
+    const int m = lead->restart;
+    const int max_cycles = lead->max_cycles;
+    const double tol = lead->tol;
     double tsap = 0, tA = 0, tgs = 0, tother = 0;
-    double2 h[32];
+    std::vector<FgcrState> st(ns);
     int e;
-    using C = std::complex<double>;
-    std::vector<C> a((size_t)m * m), cc(m), alpha(m);
-    std::vector<double> bb(m);
+    for (int i = 0; i < ns; i++) {
+        st[i].a.assign((size_t)m * m, 0);
+        st[i].cc.assign(m, 0);
+        st[i].alpha.assign(m, 0);
+        st[i].bb.assign(m, 0);
+        if ((e = ensure_basis(sys[i].c, *sys[i].sl))) return e;
+    }
+    auto nc = [&](int i) { return ncomplex(sys[i].c->g); };
+    auto Zk = [&](int i, int k) { return sys[i].sl->Z + (long)k * nc(i); };
+    auto Wk = [&](int i, int k) { return sys[i].sl->W + (long)k * nc(i); };
 
-    if (!guess) HIPCHK(c, zero(c->x, n, s));
-    HIPCHK(c, norm2(c->blas, c->b, n, s));
-    if ((e = fetch(c, h, 1, s))) return e;
-    const double bn = std::sqrt(h[0].x);
-    int steps = 0, cycles = 0, status = DDQCD_ERR_NOT_CONVERGED;
-    double rel = 0;
-    if (!std::isfinite(bn)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite right-hand side");
-    if (bn == 0) {
-        HIPCHK(c, zero(c->x, n, s));
-        status = DDQCD_OK;
-        goto done;
+    // |b| and the initial residual
+    std::vector<int> all(ns), live;
+    for (int i = 0; i < ns; i++) {
+        all[i] = i;
+        if (!guess[i]) HIPCHK(sys[i].c, zero(sys[i].sl->x, nc(i), s));
+        HIPCHK(sys[i].c, norm2(sys[i].sl->blas, sys[i].sl->b, nc(i), s));
+    }
+    if ((e = fetch_all(sys, st, all, 1, s))) return e;
+    for (int i = 0; i < ns; i++) {
+        st[i].bn = std::sqrt(st[i].h[0].x);
+        if (!std::isfinite(st[i].bn)) return fail(sys[i].c, DDQCD_ERR_NONFINITE, "non-finite right-hand side");
+        if (st[i].bn == 0) {
+            HIPCHK(sys[i].c, zero(sys[i].sl->x, nc(i), s));
+            st[i].done = true;
+            st[i].status = DDQCD_OK;
+        } else live.push_back(i);
     }
     {
         Timer t(s, &tA);
-        if ((e = apply_A64(c, c->x, c->r, s))) return e;
+        for (int i : live)
+            if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
     }
     {
         Timer t(s, &tother);
-        HIPCHK(c, residual(c->blas, c->b, c->r, n, s));
-        if ((e = fetch(c, h, 1, s))) return e;
+        for (int i : live) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
+        if ((e = fetch_all(sys, st, live, 1, s))) return e;
     }
-    rel = std::sqrt(h[0].x) / bn;
-    if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
-    if (rel <= c->tol) {
-        status = DDQCD_OK;
-        goto done;
+    for (int i : live) {
+        st[i].rel = std::sqrt(st[i].h[0].x) / st[i].bn;
+        if (!std::isfinite(st[i].rel)) return fail(sys[i].c, DDQCD_ERR_NONFINITE, "non-finite residual");
+        if (st[i].rel <= tol) {
+            st[i].done = true;
+            st[i].status = DDQCD_OK;
+        }
     }
-    for (cycles = 0; cycles < c->max_cycles;) {
-        int kend = 0;
+
+    for (int cyc = 0; cyc < max_cycles; cyc++) {
+        std::vector<int> cur;
+        for (int i = 0; i < ns; i++) {
+            st[i].in_cycle = !st[i].done;
+            st[i].kend = 0;
+            if (!st[i].done) cur.push_back(i);
+        }
+        if (cur.empty()) break;
         for (int k = 0; k < m; k++) {
-            double2 *zk = Z + (long)k * n, *wk = W + (long)k * n;
+            std::vector<int> act;
+            for (int i : cur)
+                if (st[i].in_cycle) act.push_back(i);
+            if (act.empty()) break;
+            // z_k = M r
             {
                 Timer t(s, &tsap);
-                if ((e = run_sap(c, c->r, zk, s))) return e;
+                std::vector<const double2 *> eta(ns);
+                std::vector<double2 *> out(ns);
+                std::vector<int> on(ns, 0);
+                for (int i = 0; i < ns; i++) {
+                    eta[i] = sys[i].sl->r;
+                    out[i] = Zk(i, k);
+                }
+                for (int i : act) on[i] = 1;
+                if ((e = run_sap(sys, eta, out, on, s))) return e;
             }
+            // w_k = A z_k
             {
                 Timer t(s, &tA);
-                if ((e = apply_A64(c, zk, wk, s))) return e;
+                for (int i : act)
+                    if ((e = apply_A64(sys[i].c, Zk(i, k), Wk(i, k), s))) return e;
             }
             {
                 Timer t(s, &tgs);
-                // classical Gram-Schmidt against the earlier w-hat, repeated once
-                // if the new vector lost more than half its norm
-                for (int j = 0; j < k; j++) a[(size_t)j * m + k] = 0;
-                double before = 0, wn2 = 0;
-                C wr;
-                for (int pass = 0; pass < 2; pass++) {
-                    std::vector<C> coef(k);
+                // classical Gram-Schmidt against the earlier w-hat, repeated
+                // once for a system whose new vector lost more than half its norm
+                std::vector<double> before(ns, 0), wn2(ns, 0);
+                std::vector<C> wr(ns);
+                std::vector<int> todo = act;
+                for (int pass = 0; pass < 2 && !todo.empty(); pass++) {
                     if (k > 0) {
-                        HIPCHK(c, multidot(c->blas, W, n, k, wk, n, s));
-                        if ((e = fetch(c, h, k, s))) return e;
-                        for (int j = 0; j < k; j++) {
-                            coef[j] = C(h[j].x, h[j].y);
-                            a[(size_t)j * m + k] += coef[j];
+                        for (int i : todo)
+                            HIPCHK(sys[i].c, multidot(sys[i].sl->blas, sys[i].sl->W, nc(i), k, Wk(i, k), nc(i), s));
+                        if ((e = fetch_all(sys, st, todo, k, s))) return e;
+                        for (int i : todo) {
+                            std::vector<C> coef(k);
+                            for (int j = 0; j < k; j++) {
+                                coef[j] = C(st[i].h[j].x, st[i].h[j].y);
+                                st[i].a[(size_t)j * m + k] += coef[j];
+                            }
+                            if ((e = put_coef(sys[i], coef, s))) return e;
                         }
-                        if ((e = put_coef(c, coef, s))) return e;
                     }
                     if (pass == 0) {
-                        HIPCHK(c, norm2(c->blas, wk, n, s));
-                        if ((e = fetch(c, h, 1, s))) return e;
-                        before = h[0].x;
+                        for (int i : todo) HIPCHK(sys[i].c, norm2(sys[i].sl->blas, Wk(i, k), nc(i), s));
+                        if ((e = fetch_all(sys, st, todo, 1, s))) return e;
+                        for (int i : todo) before[i] = st[i].h[0].x;
                     }
-                    HIPCHK(c, cgs_update(c->blas, wk, W, n, k, c->r, n, s));
-                    if ((e = fetch(c, h, 2, s))) return e;
-                    wn2 = h[0].x;
-                    wr = C(h[1].x, h[1].y);
-                    if (k == 0 || wn2 > 0.25 * before) break;
-                    before = wn2;
+                    for (int i : todo)
+                        HIPCHK(sys[i].c, cgs_update(sys[i].sl->blas, Wk(i, k), sys[i].sl->W, nc(i), k, sys[i].sl->r,
+                                                    nc(i), s));
+                    if ((e = fetch_all(sys, st, todo, 2, s))) return e;
+                    std::vector<int> again;
+                    for (int i : todo) {
+                        wn2[i] = st[i].h[0].x;
+                        wr[i] = C(st[i].h[1].x, st[i].h[1].y);
+                        if (k > 0 && !(wn2[i] > 0.25 * before[i])) {
+                            before[i] = wn2[i];
+                            again.push_back(i);
+                        }
+                    }
+                    todo = again;
                 }
-                bb[k] = std::sqrt(wn2);
-                if (!(bb[k] > 0) || !std::isfinite(bb[k]))
-                    return fail(c, DDQCD_ERR_NONFINITE, "breakdown: A M r vanished or is non-finite");
-                cc[k] = wr / bb[k];
-                HIPCHK(c, normalize_update(c->blas, wk, 1.0 / bb[k], c->r, make_double2(cc[k].real(), cc[k].imag()), n, s));
-                if ((e = fetch(c, h, 1, s))) return e;
+                for (int i : act) {
+                    FgcrState &f = st[i];
+                    f.bb[k] = std::sqrt(wn2[i]);
+                    if (!(f.bb[k] > 0) || !std::isfinite(f.bb[k]))
+                        return fail(sys[i].c, DDQCD_ERR_NONFINITE, "breakdown: A M r vanished or is non-finite");
+                    f.cc[k] = wr[i] / f.bb[k];
+                    HIPCHK(sys[i].c, normalize_update(sys[i].sl->blas, Wk(i, k), 1.0 / f.bb[k], sys[i].sl->r,
+                                                      make_double2(f.cc[k].real(), f.cc[k].imag()), nc(i), s));
+                }
+                if ((e = fetch_all(sys, st, act, 1, s))) return e;
             }
-            steps++;
-            kend = k + 1;
-            rel = std::sqrt(h[0].x) / bn;
-            if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
-            if (rel <= c->tol) break;
+            for (int i : act) {
+                FgcrState &f = st[i];
+                f.steps++;
+                f.kend = k + 1;
+                f.rel = std::sqrt(f.h[0].x) / f.bn;
+                if (!std::isfinite(f.rel)) return fail(sys[i].c, DDQCD_ERR_NONFINITE, "non-finite residual");
+                if (f.rel <= tol) f.in_cycle = false;
+            }
         }
+        // x += sum_k alpha_k z_k, then the true residual r = b - A x
         {
             Timer t(s, &tother);
-            for (int k = kend - 1; k >= 0; k--) {
-                C sum = cc[k];
-                for (int j = k + 1; j < kend; j++) sum -= a[(size_t)k * m + j] * alpha[j];
-                alpha[k] = sum / bb[k];
+            for (int i : cur) {
+                FgcrState &f = st[i];
+                for (int k = f.kend - 1; k >= 0; k--) {
+                    C sum = f.cc[k];
+                    for (int j = k + 1; j < f.kend; j++) sum -= f.a[(size_t)k * m + j] * f.alpha[j];
+                    f.alpha[k] = sum / f.bb[k];
+                }
+                std::vector<C> al(f.alpha.begin(), f.alpha.begin() + f.kend);
+                if ((e = put_coef(sys[i], al, s))) return e;
+                HIPCHK(sys[i].c, axpy_multi(sys[i].sl->blas, sys[i].sl->x, sys[i].sl->Z, nc(i), f.kend, nc(i), s));
+                std::fill(f.a.begin(), f.a.end(), C(0));
             }
-            std::vector<C> al(alpha.begin(), alpha.begin() + kend);
-            if ((e = put_coef(c, al, s))) return e;
-            HIPCHK(c, axpy_multi(c->blas, c->x, Z, n, kend, n, s));
         }
         {
             Timer t(s, &tA);
-            if ((e = apply_A64(c, c->x, c->r, s))) return e;
+            for (int i : cur)
+                if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
         }
         {
             Timer t(s, &tother);
-            HIPCHK(c, residual(c->blas, c->b, c->r, n, s));
-            if ((e = fetch(c, h, 1, s))) return e;
+            for (int i : cur) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
+            if ((e = fetch_all(sys, st, cur, 1, s))) return e;
         }
-        cycles++;
-        rel = std::sqrt(h[0].x) / bn;
-        if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
-        if (rel <= c->tol) {
-            status = DDQCD_OK;
-            break;
+        for (int i : cur) {
+            FgcrState &f = st[i];
+            f.cycles++;
+            f.rel = std::sqrt(f.h[0].x) / f.bn;
+            if (!std::isfinite(f.rel)) return fail(sys[i].c, DDQCD_ERR_NONFINITE, "non-finite residual");
+            if (f.rel <= tol) {
+                f.done = true;
+                f.status = DDQCD_OK;
+            }
         }
     }
-done:
-    if (info) {
-        info->converged = status == DDQCD_OK;
-        info->iters = steps;
-        info->restarts = cycles;
-        info->rel_residual = rel;
-        info->t_sap_ms = tsap;
-        info->t_A_ms = tA;
-        info->t_gs_ms = tgs;
-        info->t_other_ms = tother;
+    int status = DDQCD_OK;
+    for (int i = 0; i < ns; i++) {
+        ddqcd_info &inf = info[i];
+        inf.converged = st[i].status == DDQCD_OK;
+        inf.iters = st[i].steps;
+        inf.restarts = st[i].cycles;
+        inf.rel_residual = st[i].rel;
+        inf.t_sap_ms = tsap;
+        inf.t_A_ms = tA;
+        inf.t_gs_ms = tgs;
+        inf.t_other_ms = tother;
+        if (st[i].status != DDQCD_OK) {
+            status = DDQCD_ERR_NOT_CONVERGED;
+            sys[i].c->err = "not converged: relative residual " + std::to_string(st[i].rel);
+        }
     }
-    if (status != DDQCD_OK) c->err = "not converged: relative residual " + std::to_string(rel);
     return status;
+}
+
+// shared body of ddqcd_solve and ddqcd_solve_batch
+int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *const *b, int x_is_guess,
+                  ddqcd_info *info, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (size_t i = 0; i < sys.size(); i++) {
+        const Geo &g = sys[i].c->g;
+        HIPCHK(sys[i].c, import_spinor(g, b[i], sys[i].sl->b, P64, s));
+        if (x_is_guess) HIPCHK(sys[i].c, import_spinor(g, x[i], sys[i].sl->x, P64, s));
+    }
+    std::vector<ddqcd_info> inf(sys.size());
+    const int st = fgcr(sys, std::vector<int>(sys.size(), x_is_guess != 0), inf, s);
+    if (st != DDQCD_OK && st != DDQCD_ERR_NOT_CONVERGED) return st;
+    for (size_t i = 0; i < sys.size(); i++) HIPCHK(sys[i].c, export_spinor(sys[i].c->g, sys[i].sl->x, P64, x[i], s));
+    HIPCHK(sys[0].c, hipStreamSynchronize(s));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (size_t i = 0; i < sys.size(); i++) {
+        inf[i].t_total_ms = ms;
+        if (info) info[i] = inf[i];
+    }
+    return st;
 }
 
 bool is_pm1(double v) { return v == 1.0 || v == -1.0; }
@@ -424,11 +640,11 @@ int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double
         if (!is_pm1(boundary[m])) return DDQCD_ERR_ARG;
         if (lattice[m] < 2 || domain[m] < 2) return DDQCD_ERR_GEOMETRY;
         if (domain[m] % 2 || lattice[m] % domain[m]) return DDQCD_ERR_GEOMETRY;
-        int n = lattice[m] / domain[m];
+        const int n = lattice[m] / domain[m];
         if (n < 2 || n % 2) return DDQCD_ERR_GEOMETRY;
     }
     if (!sap_shape_supported(domain)) return DDQCD_ERR_GEOMETRY;
-    long V = (long)lattice[0] * lattice[1] * lattice[2] * lattice[3];
+    const long V = (long)lattice[0] * lattice[1] * lattice[2] * lattice[3];
     if (V * 12 > (1L << 40)) return DDQCD_ERR_GEOMETRY;
     ddqcd_ctx *c = new (std::nothrow) ddqcd_ctx();
     if (!c) return DDQCD_ERR_NOMEM;
@@ -453,8 +669,6 @@ int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double
         }
         c->dom_host[s & 1].push_back(d);
     }
-    c->order_host = c->dom_host[0];
-    c->order_host.insert(c->order_host.end(), c->dom_host[1].begin(), c->dom_host[1].end());
     *out = c;
     return DDQCD_OK;
 }
@@ -462,8 +676,8 @@ int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double
 int ddqcd_destroy(ddqcd_t c)
 {
     if (!c) return DDQCD_OK;
+    c->plans.clear();
     for (void *p : c->owned) (void)hipFree(p);
-    c->blas.release();
     delete c;
     return DDQCD_OK;
 }
@@ -514,21 +728,7 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
     const size_t V = (size_t)g.V;
     if (c->device < 0) {
         HIPCHK(c, hipGetDevice(&c->device));
-        HIPCHK(c, c->blas.init());
-        for (int col = 0; col < 2; col++) {
-            if ((e = alloc(c, &c->d_dom[col], c->dom_host[col].size() * sizeof(int)))) return e;
-            HIPCHK(c, hipMemcpy(c->d_dom[col], c->dom_host[col].data(), c->dom_host[col].size() * sizeof(int),
-                                hipMemcpyHostToDevice));
-        }
         if ((e = alloc(c, &c->d_flag, sizeof(int)))) return e;
-        if ((e = alloc(c, &c->d_epoch, sizeof(int) * g.nd))) return e;
-        if ((e = alloc(c, &c->d_counter, sizeof(int)))) return e;
-        if ((e = alloc(c, &c->d_qerr, sizeof(int)))) return e;
-        if ((e = alloc(c, &c->d_order, sizeof(int) * g.nd))) return e;
-        HIPCHK(c, hipMemcpy(c->d_order, c->order_host.data(), sizeof(int) * g.nd, hipMemcpyHostToDevice));
-        HIPCHK(c, queue_reset_epochs(c->d_epoch, g.nd, c->d_qerr, s));
-        c->epoch_base = 0;
-        HIPCHK(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
         if ((e = alloc(c, &c->U64, V * 4 * 9 * 16))) return e;
         if ((e = dev_alloc(c, &c->U32, V * 4 * 6 * 8))) return e;
         if ((e = dev_alloc(c, &c->U16, V * 4 * 6 * 4))) return e;
@@ -539,6 +739,7 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
         if ((e = dev_alloc(c, &c->Cs32, V * 36 * 8))) return e;
         if ((e = dev_alloc(c, &c->Cs16, V * 36 * 4))) return e;
     }
+    c->loaded = false;
     HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
     HIPCHK(c, count_nonfinite((const double2 *)U, (long)V * 36, c->d_flag, s));
     int bad = 0;
@@ -566,20 +767,22 @@ int ddqcd_apply_D(ddqcd_t c, double *out, const double *in, int nrhs, int prec, 
     if (!c) return DDQCD_ERR_ARG;
     if (!out || !in || nrhs < 1 || out == in) return fail(c, DDQCD_ERR_ARG, "bad apply_D arguments");
     if (prec != DDQCD_FP64 && prec != DDQCD_FP32 && prec != DDQCD_FP16) return fail(c, DDQCD_ERR_ARG, "bad precision");
-    if (!c->loaded) return fail(c, DDQCD_ERR_STATE, "apply_D before load_gauge");
-    int e = check_device(c);
-    if (e || (e = ensure_spinor_tmp(c))) return e;
+    int e = check_ready(c, "apply_D");
+    if (e || (e = ensure_slots(c, 1))) return e;
     hipStream_t s = (hipStream_t)stream;
     const Geo &g = c->g;
     const long n = ncomplex(g);
+    if (prec != DDQCD_FP64 && !c->t_lo_in) {
+        if ((e = dev_alloc(c, &c->t_lo_in, (size_t)n * 8))) return e;
+        if ((e = dev_alloc(c, &c->t_lo_out, (size_t)n * 8))) return e;
+    }
+    Slot &sl = *c->slots[0];
+    void *ti = prec == DDQCD_FP64 ? (void *)sl.b : c->t_lo_in;
+    void *to = prec == DDQCD_FP64 ? (void *)sl.x : c->t_lo_out;
     for (int k = 0; k < nrhs; k++) {
-        const double *ik = in + (size_t)k * n * 2;
-        double *ok = out + (size_t)k * n * 2;
-        void *ti = prec == DDQCD_FP64 ? (void *)c->t_in : c->t_lo_in;
-        void *to = prec == DDQCD_FP64 ? (void *)c->t_out : c->t_lo_out;
-        HIPCHK(c, import_spinor(g, ik, ti, prec, s));
+        HIPCHK(c, import_spinor(g, in + (size_t)k * n * 2, ti, prec, s));
         HIPCHK(c, apply_A(g, ti, to, links_for(c, prec), clover_for(c, prec), prec, s));
-        HIPCHK(c, export_spinor(g, to, prec, ok, s));
+        HIPCHK(c, export_spinor(g, to, prec, out + (size_t)k * n * 2, s));
     }
     return DDQCD_OK;
 }
@@ -588,17 +791,23 @@ int ddqcd_sap(ddqcd_t c, double *out, const double *in, int nrhs, void *stream)
 {
     if (!c) return DDQCD_ERR_ARG;
     if (!out || !in || nrhs < 1 || out == in) return fail(c, DDQCD_ERR_ARG, "bad sap arguments");
-    if (!c->loaded) return fail(c, DDQCD_ERR_STATE, "sap before load_gauge");
-    int e = check_device(c);
-    if (e || (e = ensure_spinor_tmp(c))) return e;
+    int e = check_ready(c, "sap");
+    if (e || (e = ensure_slots(c, nrhs))) return e;
     hipStream_t s = (hipStream_t)stream;
     const Geo &g = c->g;
     const long n = ncomplex(g);
+    std::vector<Sys> sys;
+    std::vector<const double2 *> eta;
+    std::vector<double2 *> o;
     for (int k = 0; k < nrhs; k++) {
-        HIPCHK(c, import_spinor(g, in + (size_t)k * n * 2, c->t_in, P64, s));
-        if ((e = run_sap(c, c->t_in, c->t_out, s))) return e;
-        HIPCHK(c, export_spinor(g, c->t_out, P64, out + (size_t)k * n * 2, s));
+        Slot *sl = c->slots[k].get();
+        sys.push_back({c, sl, k});
+        HIPCHK(c, import_spinor(g, in + (size_t)k * n * 2, sl->b, P64, s));
+        eta.push_back(sl->b);
+        o.push_back(sl->x);
     }
+    if ((e = run_sap(sys, eta, o, std::vector<int>(nrhs, 1), s))) return e;
+    for (int k = 0; k < nrhs; k++) HIPCHK(c, export_spinor(g, c->slots[k]->x, P64, out + (size_t)k * n * 2, s));
     return DDQCD_OK;
 }
 
@@ -606,27 +815,44 @@ int ddqcd_solve(ddqcd_t c, double *x, const double *b, int nrhs, int x_is_guess,
 {
     if (!c) return DDQCD_ERR_ARG;
     if (!x || !b || nrhs < 1 || x == b) return fail(c, DDQCD_ERR_ARG, "bad solve arguments");
-    if (!c->loaded) return fail(c, DDQCD_ERR_STATE, "solve before load_gauge");
-    int e = check_device(c);
-    if (e || (e = ensure_solver_space(c))) return e;
-    hipStream_t s = (hipStream_t)stream;
-    const Geo &g = c->g;
-    const long n = ncomplex(g);
-    int status = DDQCD_OK;
+    int e = check_ready(c, "solve");
+    if (e || (e = ensure_slots(c, nrhs))) return e;
+    const long n = ncomplex(c->g);
+    std::vector<Sys> sys;
+    std::vector<double *> xs;
+    std::vector<const double *> bs;
     for (int k = 0; k < nrhs; k++) {
-        auto t0 = std::chrono::steady_clock::now();
-        ddqcd_info inf{};
-        HIPCHK(c, import_spinor(g, b + (size_t)k * n * 2, c->b, P64, s));
-        if (x_is_guess) HIPCHK(c, import_spinor(g, x + (size_t)k * n * 2, c->x, P64, s));
-        int st = fgcr(c, x_is_guess != 0, &inf, s);
-        if (st != DDQCD_OK && st != DDQCD_ERR_NOT_CONVERGED) return st;
-        HIPCHK(c, export_spinor(g, c->x, P64, x + (size_t)k * n * 2, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        inf.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        if (info) info[k] = inf;
-        if (st != DDQCD_OK) status = st;
+        sys.push_back({c, c->slots[k].get(), k});
+        xs.push_back(x + (size_t)k * n * 2);
+        bs.push_back(b + (size_t)k * n * 2);
     }
-    return status;
+    return solve_systems(sys, xs.data(), bs.data(), x_is_guess, info, (hipStream_t)stream);
+}
+
+int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double *const *b, int x_is_guess,
+                      ddqcd_info *info, void *stream)
+{
+    if (!ctxs || n < 1 || !x || !b) return DDQCD_ERR_ARG;
+    for (int i = 0; i < n; i++)
+        if (!ctxs[i]) return DDQCD_ERR_ARG;
+    for (int i = 0; i < n; i++)
+        if (!x[i] || !b[i] || (const double *)x[i] == b[i])
+            return fail(ctxs[i], DDQCD_ERR_ARG, "bad solve_batch arguments for system " + std::to_string(i));
+    ddqcd_t c0 = ctxs[0];
+    std::vector<Sys> sys;
+    std::map<ddqcd_t, int> used;
+    for (int i = 0; i < n; i++) {
+        ddqcd_t c = ctxs[i];
+        int e = check_ready(c, "solve_batch");
+        if (e) return e;
+        if (c->restart != c0->restart || c->tol != c0->tol || c->max_cycles != c0->max_cycles ||
+            c->n_cycles != c0->n_cycles)
+            return fail(c, DDQCD_ERR_ARG, "batched contexts need equal solver settings and SAP cycle counts");
+        const int k = used[c]++;
+        if ((e = ensure_slots(c, k + 1))) return e;
+        sys.push_back({c, c->slots[k].get(), k});
+    }
+    return solve_systems(sys, x, b, x_is_guess, info, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -30,11 +30,18 @@ hipError_t count_nonfinite(const double2 *v, long n, int *cnt, hipStream_t s);
 hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
                    hipStream_t s);
 
-// One SAP half-sweep over the domains of one colour.
+// What one visit of a domain reads and writes.
+struct Visit {
+    int first;      // first visit in this preconditioner call: residual is eta
+    int faces_in;   // add the neighbours' boundary terms
+    int last;       // last visit: write psi to the FP64 output
+    int faces_out;  // write this domain's boundary terms
+    int res_out;    // store the block residual
+};
+
+// Arguments of the block solves of one system (one lattice, one right-hand side).
 struct SapArgs {
     Geo g;
-    const int *dom;     // domains of the colour being swept
-    int ndom;
     int first;          // first visit of these domains: residual is eta
     int faces_in;       // add the boundary terms of the previous half-sweep
     int last;           // last visit: write psi (+ delta) to out
@@ -51,6 +58,7 @@ struct SapArgs {
     const void *links;  // [d][mu][9 or 6][Vd]
     const void *cs;     // C_e on even / C_o^-1 on odd sites [d][36][Vd]
     void *rho_tmp;      // odd-site right-hand sides [d][12][Vd/2] when not kept in LDS
+    int active;         // 0: skip this system (already converged)
 };
 // The persistent form: every block solve of one preconditioner call in one
 // launch, dequeued from a work queue and ordered by per-domain epoch counters.
@@ -68,7 +76,11 @@ hipError_t queue_reset_epochs(int *epoch, int nd, int *error, hipStream_t s);
 bool sap_shape_supported(const int b[4]);
 bool sap_prec_supported(const int b[4], int prec);
 long sap_face_sites(const int b[4]);
-hipError_t sap_sweep(const SapArgs &a, int prec, hipStream_t s);
+int sap_shape_id(const int b[4]);
+// One colour of one half-sweep for a list of (system, domain) items; args and
+// items are device arrays.  All systems share one domain shape (shape id).
+hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,
+                           hipStream_t s);
 
 // ---- FP64 linear algebra on flat complex vectors (double2) ---------------
 struct Blas {

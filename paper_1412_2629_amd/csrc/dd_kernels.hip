@@ -320,42 +320,39 @@ hipError_t clover_schur(const Geo &g, const double2 *C64, double2 *Cs64, int *ba
 // global operator A (Sec. II-B, Eqs. 1-2): one thread per site
 // ===========================================================================
 
-template <int MU, typename T, typename SI, typename G, int NLC>
-__device__ __forceinline__ void a_hops(const Geo &g, const int x[4], int d, int loc, const v2<SI> *in,
-                                       const v2<G> *links, cx<T> acc[12])
+// one hop: DIR = +1 forward, -1 backward
+template <int MU, int DIR, typename T, typename SI, typename G, int NLC>
+__device__ __forceinline__ void a_hop(const Geo &g, const int x[4], int d, int loc, const v2<SI> *in,
+                                      const v2<G> *links, cx<T> acc[12])
 {
     const long Vd = g.Vd;
     int y[4] = {x[0], x[1], x[2], x[3]};
-    cx<T> v[12], h[6], uh[6];
-    // forward: -1/2 (1 - gamma_mu) U_mu(x) psi(x + mu)
     bool wrap = false;
-    y[MU] = x[MU] + 1;
-    if (y[MU] == g.L[MU]) { y[MU] = 0; wrap = true; }
-    long J = encode(g, y);
-    int dj = (int)(J / Vd), lj = (int)(J - (long)dj * Vd);
+    if constexpr (DIR > 0) {
+        y[MU] = x[MU] + 1;
+        if (y[MU] == g.L[MU]) { y[MU] = 0; wrap = true; }
+    } else {
+        y[MU] = x[MU] - 1;
+        if (y[MU] < 0) { y[MU] = g.L[MU] - 1; wrap = true; }
+    }
+    const long J = encode(g, y);
+    const int dj = (int)(J / Vd), lj = (int)(J - (long)dj * Vd);
+    cx<T> v[12], h[6], uh[6];
 #pragma unroll
     for (int k = 0; k < 12; k++) v[k] = ld<T, SI>(in, ((long)dj * 12 + k) * Vd + lj);
-    proj<MU, -1>(v, h);
-    {
+    if constexpr (DIR > 0) {
+        // -1/2 (1 - gamma_mu) U_mu(x) psi(x + mu)
+        proj<MU, -1>(v, h);
         su3<T> U = ld_link<T, G, NLC>(links, ((long)d * 4 + MU) * NLC * Vd + loc, Vd);
         su3_mul(U, h, uh);
-    }
-    recon_acc<MU, -1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
-    // backward: -1/2 (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
-    wrap = false;
-    y[MU] = x[MU] - 1;
-    if (y[MU] < 0) { y[MU] = g.L[MU] - 1; wrap = true; }
-    J = encode(g, y);
-    dj = (int)(J / Vd);
-    lj = (int)(J - (long)dj * Vd);
-#pragma unroll
-    for (int k = 0; k < 12; k++) v[k] = ld<T, SI>(in, ((long)dj * 12 + k) * Vd + lj);
-    proj<MU, +1>(v, h);
-    {
+        recon_acc<MU, -1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
+    } else {
+        // -1/2 (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu)
+        proj<MU, +1>(v, h);
         su3<T> U = ld_link<T, G, NLC>(links, ((long)dj * 4 + MU) * NLC * Vd + lj, Vd);
         su3_dag_mul(U, h, uh);
+        recon_acc<MU, +1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
     }
-    recon_acc<MU, +1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
 }
 
 template <typename T, typename SI, typename SO, typename G, int NLC>
@@ -374,10 +371,23 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const v2<SI> *in, v2<SO>
         for (int k = 0; k < 12; k++) s[k] = ld<T, SI>(in, ((long)d * 12 + k) * Vd + loc);
         clover_apply<T, G>(clov, (long)d * 36 * Vd + loc, Vd, s, acc);
     }
-    a_hops<0, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
-    a_hops<1, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
-    a_hops<2, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
-    a_hops<3, T, SI, G, NLC>(g, x, d, loc, in, links, acc);
+    // The eight hops one after another (a loop the compiler keeps rolled): only
+    // one neighbour's spinor and link are live at a time.  Unrolled, the
+    // compiler issues every load of the site up front, which needs several
+    // hundred registers and spills to scratch.
+#pragma unroll 1
+    for (int k = 0; k < 8; k++) {
+        switch (k) {
+            case 0: a_hop<0, +1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 1: a_hop<0, -1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 2: a_hop<1, +1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 3: a_hop<1, -1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 4: a_hop<2, +1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 5: a_hop<2, -1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            case 6: a_hop<3, +1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+            default: a_hop<3, -1, T, SI, G, NLC>(g, x, d, loc, in, links, acc); break;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 12; k++) st<T, SO>(out, ((long)d * 12 + k) * Vd + loc, acc[k]);
 }

@@ -318,7 +318,7 @@ __device__ __forceinline__ void write_site(const SapArgs &a, int d, const int l[
 }
 
 template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool RHO_LDS>
-__global__ __launch_bounds__(Sh::VH) void k_sap_sweep(SapArgs a)
+__device__ __forceinline__ void pair_block_solve(const SapArgs &a, const int d)
 {
     constexpr int VD = Sh::VD, VH = Sh::VH;
     __shared__ cx<T> she[12][VH];                                  // even-site spinor being hopped
@@ -327,7 +327,6 @@ __global__ __launch_bounds__(Sh::VH) void k_sap_sweep(SapArgs a)
     __shared__ cx<T> shr[RHO_LDS ? 12 : 1][RHO_LDS ? VH : 1];      // rho on the odd sites
     __shared__ T red[VH >= 64 ? 3 * (VH / 64) : 3 * VH];
 
-    const int d = a.dom[blockIdx.x];
     const int t = threadIdx.x;
     const int loc_e = t, loc_o = VH + t;
     int le[4], lo[4];
@@ -482,15 +481,6 @@ __device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12
     clover_block_reg<T, G>(cl, in, out);
     clover_block_reg<T, G>(cl + 18, in + 6, out + 6);
 }
-
-// what one visit of a domain reads and writes
-struct Visit {
-    int first;      // first visit in this preconditioner call: residual is eta
-    int faces_in;   // add the neighbours' boundary terms
-    int last;       // last visit: write psi to the FP64 output
-    int faces_out;  // write this domain's boundary terms
-    int res_out;    // store the block residual
-};
 
 template <class Sh, typename SS, typename G, bool SCALED>
 __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
@@ -672,10 +662,36 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 }
 
 
+// ---- batched half-sweeps ------------------------------------------------------
+//
+// One launch covers one colour of one half-sweep for many systems (right-hand
+// sides and lattices of one domain shape): workgroup i takes item i = (system,
+// domain) and that system's arguments.  Items with system < 0 are padding;
+// systems with active == 0 (already converged) are skipped.
+
 template <class Sh, typename SS, typename G, bool SCALED>
-__global__ __launch_bounds__(Sh::VD) void k_sap_lds(SapArgs a)
+__global__ __launch_bounds__(Sh::VD) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
 {
-    lds_block_solve<Sh, SS, G, SCALED>(a, a.dom[blockIdx.x], Visit{a.first, a.faces_in, a.last, a.faces_out, a.res_out});
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const SapArgs a = args[it.x];
+    if (!a.active) return;
+    lds_block_solve<Sh, SS, G, SCALED>(a, it.y, v);
+}
+
+template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool RHO_LDS>
+__global__ __launch_bounds__(Sh::VH) void k_sap_sweep(const SapArgs *args, const int2 *items, Visit v)
+{
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    SapArgs a = args[it.x];
+    if (!a.active) return;
+    a.first = v.first;
+    a.faces_in = v.faces_in;
+    a.last = v.last;
+    a.faces_out = v.faces_out;
+    a.res_out = v.res_out;
+    pair_block_solve<Sh, T, SS, PS, G, NLC, SCALED, RHO_LDS>(a, it.y);
 }
 
 // ---- persistent work-queue kernel -------------------------------------------
@@ -773,20 +789,20 @@ __global__ void k_epoch_reset(int *epoch, int nd, int *error)
 
 // ---- dispatch ---------------------------------------------------------------
 
-template <class Sh> static hipError_t launch_shape(const SapArgs &a, int prec, hipStream_t s)
+template <class Sh>
+static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
 {
-    dim3 grid(a.ndom);
     if (prec == P64)
-        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), grid, dim3(Sh::VH), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
+                           dim3(Sh::VH), 0, s, args, items, v);
     else if (prec == P32)
-        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, false>), grid, dim3(Sh::VD), 0, s, a);
+        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, false>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
     else
-        hipLaunchKernelGGL((k_sap_lds<Sh, half_t, half_t, true>), grid, dim3(Sh::VD), 0, s, a);
+        hipLaunchKernelGGL((k_sap_lds<Sh, half_t, half_t, true>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
     return hipGetLastError();
 }
 
-static int shape_id(const int b[4])
+int sap_shape_id(const int b[4])
 {
     if (b[0] == 2 && b[1] == 2 && b[2] == 2 && b[3] == 2) return 0;
     if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 1;
@@ -794,12 +810,12 @@ static int shape_id(const int b[4])
     return -1;
 }
 
-bool sap_shape_supported(const int b[4]) { return shape_id(b) >= 0; }
+bool sap_shape_supported(const int b[4]) { return sap_shape_id(b) >= 0; }
 
 // FP64 block solves are built for 2^4 domains only: on larger domains the
 // FP64 instantiation spills registers to scratch memory, and that variant is
 // switched off until it is shown correct on the device.
-bool sap_prec_supported(const int b[4], int prec) { return shape_id(b) >= 0 && (prec != P64 || shape_id(b) == 0); }
+bool sap_prec_supported(const int b[4], int prec) { return sap_shape_id(b) >= 0 && (prec != P64 || sap_shape_id(b) == 0); }
 
 long sap_face_sites(const int b[4])
 {
@@ -826,7 +842,7 @@ template <class Sh> static hipError_t launch_queue(const SapArgs &a, const Queue
 hipError_t sap_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s)
 {
     if (prec == P64 || !sap_prec_supported(a.g.b, prec)) return hipErrorInvalidValue;
-    switch (shape_id(a.g.b)) {
+    switch (sap_shape_id(a.g.b)) {
         case 0: return launch_queue<Shape<2, 2, 2, 2>>(a, q, prec, n_cu, s);
         case 1: return launch_queue<Shape<4, 4, 4, 4>>(a, q, prec, n_cu, s);
         case 2: return launch_queue<Shape<8, 4, 4, 4>>(a, q, prec, n_cu, s);
@@ -840,13 +856,15 @@ hipError_t queue_reset_epochs(int *epoch, int nd, int *error, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t sap_sweep(const SapArgs &a, int prec, hipStream_t s)
+hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,
+                           hipStream_t s)
 {
-    if (!sap_prec_supported(a.g.b, prec)) return hipErrorInvalidValue;
-    switch (shape_id(a.g.b)) {
-        case 0: return launch_shape<Shape<2, 2, 2, 2>>(a, prec, s);
-        case 1: return launch_shape<Shape<4, 4, 4, 4>>(a, prec, s);
-        case 2: return launch_shape<Shape<8, 4, 4, 4>>(a, prec, s);
+    if (nitems <= 0) return hipSuccess;
+    if (prec == P64 && shape != 0) return hipErrorInvalidValue;
+    switch (shape) {
+        case 0: return launch_batch<Shape<2, 2, 2, 2>>(args, items, nitems, prec, v, s);
+        case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, v, s);
+        case 2: return launch_batch<Shape<8, 4, 4, 4>>(args, items, nitems, prec, v, s);
         default: return hipErrorInvalidValue;
     }
 }

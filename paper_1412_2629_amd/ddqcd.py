@@ -18,7 +18,8 @@ PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP1
 SCHED_SWEEPS, SCHED_QUEUE = 0, 1
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_solver", "ddqcd_load_gauge",
-           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_last_error", "ddqcd_status_string"]
+           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_last_error",
+           "ddqcd_status_string"]
 
 
 class Info(ctypes.Structure):
@@ -55,6 +56,8 @@ def lib():
         L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
         L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
         L.ddqcd_solve.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
+        L.ddqcd_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp), i,
+                                        ctypes.POINTER(Info), vp]
         L.ddqcd_last_error.argtypes = [vp]
         L.ddqcd_last_error.restype = ctypes.c_char_p
         L.ddqcd_status_string.argtypes = [i]
@@ -158,3 +161,25 @@ class Context:
         if check and st not in (OK, ERR_NOT_CONVERGED):
             self._check(st, "solve")
         return x, [i.as_dict() for i in infos], st
+
+
+def solve_batch(contexts, bs, x0s=None, check=True):
+    """Solves contexts[i] x_i = bs[i] for all i at once (ddqcd_solve_batch).
+
+    bs[i] is one (V_i, 4, 3) field of contexts[i]; a context may appear more
+    than once.  Returns ([x_i], [info dicts], status)."""
+    import torch
+    n = len(contexts)
+    assert len(bs) == n and n > 0
+    for c, b in zip(contexts, bs):
+        assert b.shape == (c.V, 4, 3), b.shape
+    xs = [torch.zeros_like(b) if x0s is None else x0s[i].clone() for i, b in enumerate(bs)]
+    hs = (ctypes.c_void_p * n)(*[c._h for c in contexts])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x, "x").value for x in xs])
+    bp = (ctypes.c_void_p * n)(*[_ptr(b, "b").value for b in bs])
+    infos = (Info * n)()
+    st = lib().ddqcd_solve_batch(hs, n, xp, bp, 0 if x0s is None else 1, infos, _stream())
+    if check and st not in (OK, ERR_NOT_CONVERGED):
+        msg = lib().ddqcd_last_error(contexts[0]._h).decode()
+        raise DDQCDError(st, f"solve_batch: {status_string(st)}: {msg}")
+    return xs, [i.as_dict() for i in infos], st

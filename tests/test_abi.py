@@ -87,6 +87,29 @@ def test_create_settings_and_state_errors():
     assert L.ddqcd_destroy(None) == ddqcd.OK
 
 
+def test_solve_batch_host_checks():
+    L = ddqcd.lib()
+    st1, h1 = _create()
+    st2, h2 = _create((8, 8, 8, 16), (4, 4, 4, 4))
+    assert st1 == st2 == ddqcd.OK
+    try:
+        vp = ctypes.c_void_p
+        hs = (vp * 2)(h1.value, h2.value)
+        xs = (vp * 2)(4096, 8192)
+        bs = (vp * 2)(12288, 16384)
+        assert L.ddqcd_solve_batch(None, 2, xs, bs, 0, None, None) == ddqcd.ERR_ARG
+        assert L.ddqcd_solve_batch(hs, 0, xs, bs, 0, None, None) == ddqcd.ERR_ARG
+        assert L.ddqcd_solve_batch((vp * 2)(h1.value, None), 2, xs, bs, 0, None, None) == ddqcd.ERR_ARG
+        assert L.ddqcd_solve_batch(hs, 2, (vp * 2)(4096, None), bs, 0, None, None) == ddqcd.ERR_ARG
+        assert L.ddqcd_solve_batch(hs, 2, xs, (vp * 2)(4096, 16384), 0, None, None) == ddqcd.ERR_ARG  # aliasing
+        # no gauge field loaded: rejected before any device work
+        assert L.ddqcd_solve_batch(hs, 2, xs, bs, 0, None, None) == ddqcd.ERR_STATE
+        assert b"load_gauge" in L.ddqcd_last_error(h1)
+    finally:
+        assert L.ddqcd_destroy(h1) == ddqcd.OK
+        assert L.ddqcd_destroy(h2) == ddqcd.OK
+
+
 def test_status_strings():
     assert ddqcd.status_string(ddqcd.ERR_NOT_CONVERGED) == "DDQCD_ERR_NOT_CONVERGED"
     assert ddqcd.status_string(99) == "unknown status"

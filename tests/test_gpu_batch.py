@@ -1,0 +1,113 @@
+"""Batched systems on the GPU: many right-hand sides of one lattice, and many
+lattices of different sizes, domain shapes and block-solve precisions solved
+together (ddqcd_sap with nrhs > 1, ddqcd_solve_batch).
+
+Each system in a batch runs exactly the arithmetic it runs alone (one
+workgroup per (system, domain), per-system reductions), so batched results
+are compared bit for bit with single-system calls, and against the oracle to
+the solve bar: true residual <= 1e-10 with the oracle's A, solution within
+1e-8 of the oracle's solve to 1e-12.
+"""
+import numpy as np
+import pytest
+
+from tests.gpu_cases import BC, SMALL, dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("ci,prec", [(0, "f64"), (0, "f16"), (2, "f32"), (2, "f16"), (3, "f32")],
+                         ids=lambda v: str(v))
+def test_sap_nrhs_equals_single(ci, prec):
+    case = SMALL[ci]
+    ctx = case.context(prec)
+    etas = np.stack([case.source(40 + k) for k in range(3)])
+    got = host(ctx.sap(dev(etas)))
+    for k in range(3):
+        alone = host(ctx.sap(dev(etas[k])))
+        assert np.array_equal(got[k], alone), (case, prec, k)
+
+
+def _batch_systems():
+    """(case, prec, n_mr, source seed): four block-solve groups (2^4 FP64, 2^4
+    FP32, 4^4 FP16, 8x4^3 FP32), two right-hand sides on one lattice."""
+    return [(SMALL[2], "f16", 5, 50), (SMALL[0], "f32", 4, 51), (SMALL[2], "f16", 5, 52),
+            (SMALL[3], "f32", 5, 53), (SMALL[1], "f64", 3, 54)]
+
+
+def test_solve_batch_mixed_lattices(oracle):
+    from paper_1412_2629_amd import ddqcd
+    n_cycles = 4
+    ctxs, cache = [], {}
+    for case, prec, n_mr, _ in _batch_systems():
+        key = (case.name, prec)
+        if key not in cache:
+            c = case.context()
+            c.set_sap(n_cycles, n_mr, prec)
+            c.set_solver(16, 1e-10, 64)
+            cache[key] = c
+        ctxs.append(cache[key])
+    srcs = [case.source(seed) for case, _, _, seed in _batch_systems()]
+    xs, infos, st = ddqcd.solve_batch(ctxs, [dev(f) for f in srcs])
+    assert st == ddqcd.OK
+    for (case, prec, n_mr, seed), c, f, x, inf in zip(_batch_systems(), ctxs, srcs, xs, infos):
+        x = host(x)
+        # the same system alone: the same iterate, bit for bit
+        x1, info1, st1 = c.solve(dev(f))
+        assert st1 == ddqcd.OK
+        assert info1[0]["iters"] == inf["iters"]
+        assert np.array_equal(host(x1), x), (case, prec)
+        # against the oracle
+        x_or, st_or, _, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=n_cycles,
+                                        n_mr=n_mr, restart=16, tol=1e-12)
+        assert st_or == 0
+        true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+        err = rel(x, x_or)
+        print(f"{case} {prec}: steps {inf['iters']}, true residual {true_res:.2e}, solution error {err:.2e}")
+        assert inf["converged"] == 1 and true_res <= 1e-10 and err <= 1e-8
+
+
+def test_solve_batch_uneven_convergence(oracle):
+    """Systems that converge at once (zero source, exact guess) stop while the
+    others go on; a not-converged system is reported as such."""
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[2]
+    ctx = case.context("f32")
+    ctx.set_solver(16, 1e-10, 64)
+    f = case.source(60)
+    x_ref, info_ref, _ = ctx.solve(dev(f))
+    zero = np.zeros_like(f)
+    xs, infos, st = ddqcd.solve_batch([ctx, ctx, ctx], [dev(f), dev(zero), dev(f)],
+                                      x0s=[dev(zero), dev(zero), x_ref])
+    assert st == ddqcd.OK
+    assert infos[0]["iters"] == info_ref[0]["iters"]
+    assert np.array_equal(host(xs[0]), host(x_ref))
+    assert infos[1]["iters"] == 0 and not np.any(host(xs[1]))
+    assert infos[2]["iters"] == 0 and np.array_equal(host(xs[2]), host(x_ref))
+    # a cycle limit too small for one system: that one is reported not converged
+    hard = case.context("f32")
+    hard.set_solver(2, 1e-10, 1)
+    easy = SMALL[0].context("f32")
+    easy.set_sap(case.n_cycles, 4, "f32")
+    easy.set_solver(2, 1e-10, 1)
+    xs, infos, st = ddqcd.solve_batch([hard, easy], [dev(f), dev(np.zeros(SMALL[0].V * 12).reshape(-1, 4, 3))])
+    assert st == ddqcd.ERR_NOT_CONVERGED
+    assert infos[0]["converged"] == 0 and infos[1]["converged"] == 1
+
+
+def test_solve_batch_rejects_mixed_settings():
+    from paper_1412_2629_amd import ddqcd
+    a = SMALL[2].context("f32")
+    b = SMALL[3].context("f32")
+    b.set_solver(8, 1e-10, 64)
+    f_a, f_b = SMALL[2].source(70), SMALL[3].source(71)
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ddqcd.solve_batch([a, b], [dev(f_a), dev(f_b)])
+    assert e.value.status == ddqcd.ERR_ARG

@@ -92,3 +92,60 @@ def test_solve_true_residual(name, oracle):
         err = rel(x, x_or)
         print(f"C2: solution error vs oracle {err:.3e} (oracle {steps} steps)")
         assert err <= 1e-8
+
+
+def test_c4_twelve_point_sources(oracle):
+    """12 point sources (every spin and colour at the origin) on the 32^3x64
+    lattice, solved together.  Every solution's true residual is evaluated
+    with the oracle's operator at every site; right-hand side 5 alone gives
+    the same iterate bit for bit."""
+    w = configs.C4
+    _, U, _ = fields("C3")
+    ctx = context(w, U)
+    srcs = np.stack([inputs.point_source(w.lattice, 0, s, c) for s in range(4) for c in range(3)])
+    x, infos, st = ctx.solve(dev(srcs))
+    assert st == 0, infos
+    print(f"C4: FGCR steps {[i['iters'] for i in infos]}, batch {infos[0]['t_total_ms']:.1f} ms", flush=True)
+    xh = host(x)
+    all_sites = np.arange(w.volume, dtype=np.int64)
+    for k in range(12):
+        Ax = oracle.apply_A_sites(w.lattice, w.bc, U, w.kappa, w.csw, xh[k], all_sites)
+        true_res = rel(Ax, srcs[k])
+        print(f"C4 rhs {k}: true residual (oracle A) {true_res:.3e}", flush=True)
+        assert true_res <= 1e-10
+    x5, info5, st5 = ctx.solve(dev(srcs[5]))
+    assert st5 == 0 and info5[0]["iters"] == infos[5]["iters"]
+    assert np.array_equal(host(x5), xh[5])
+
+
+def test_c5_uneven_batch(oracle):
+    """The 24-lattice uneven batch solved in one ddqcd_solve_batch call: every
+    solution's true residual with the oracle's operator; the smallest lattice
+    against the oracle's own solve; two lattices alone give the same iterate
+    bit for bit."""
+    from paper_1412_2629_amd import ddqcd
+    ws = configs.uneven_batch()
+    ctxs, Us, fs = [], [], []
+    for j, w in enumerate(ws):
+        print(f"[fullsize] generating uneven batch lattice {j} {w.lattice}", flush=True)
+        U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
+        Us.append(U)
+        fs.append(inputs.gaussian_source(w.lattice, w.source_seed))
+        ctxs.append(context(w, U))
+    xs, infos, st = ddqcd.solve_batch(ctxs, [dev(f) for f in fs])
+    assert st == ddqcd.OK, infos
+    print(f"C5: batch {infos[0]['t_total_ms']:.1f} ms, steps {[i['iters'] for i in infos]}", flush=True)
+    for j, (w, U, f, x) in enumerate(zip(ws, Us, fs, xs)):
+        C = oracle.clover_field(w.lattice, U, w.kappa, w.csw)
+        true_res = rel(oracle.apply_A(w.lattice, w.bc, U, C, host(x)), f)
+        print(f"C5 lattice {j} {w.lattice}: true residual (oracle A) {true_res:.3e}", flush=True)
+        assert true_res <= 1e-10
+    w, U, f = ws[0], Us[0], fs[0]
+    C = oracle.clover_field(w.lattice, U, w.kappa, w.csw)
+    x_or, st_or, _, _ = oracle.fgcr(w.lattice, w.domain, w.bc, U, C, oracle.clover_inverse(C), f,
+                                    n_cycles=w.n_cycles, n_mr=w.n_mr, restart=w.restart, tol=1e-12)
+    assert st_or == 0 and rel(host(xs[0]), x_or) <= 1e-8
+    for j in (0, len(ws) - 1):
+        x1, info1, st1 = ctxs[j].solve(dev(fs[j]))
+        assert st1 == 0 and info1[0]["iters"] == infos[j]["iters"]
+        assert np.array_equal(host(x1), host(xs[j]))
