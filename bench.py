@@ -6,7 +6,11 @@ of the hot path: FP64 operator, Schwarz preconditioner with MR block solves,
 Gram-Schmidt, solution update), inputs resident in HBM, gauge field and
 clover term loaded beforehand.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload C2|C3|C1]
+  python bench.py [--steps K] [--warmup W] [--workload C2|C3|C4|C5|C1]
+
+C2 (16^3x32, FP32 block solves) is the default.  C4 solves 12 point sources
+on the 32^3x64 lattice together, C5 the 24-lattice uneven batch in one
+ddqcd_solve_batch call; for them one step is the whole batch.
 """
 import argparse
 import json
@@ -20,10 +24,63 @@ sys.path.insert(0, ROOT)
 METRIC = "solve time @rel.res 1e-10; SAP Dslash Gflop/s & %HBM/FP32 peak; mixed vs FP64"
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32
 HBM_PEAK_GBS = 8000.0
+CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+class System:
+    """One lattice of the benchmark with its sources (one or more right-hand sides)."""
+
+    def __init__(self, w, U, srcs, schedule="sweeps"):
+        import numpy as np
+        import torch
+
+        from paper_1412_2629_amd import ddqcd
+        self.w, self.U, self.srcs = w, U, srcs
+        dev = torch.device("cuda:0")
+        self.ctx = ddqcd.Context(w.lattice, w.domain, w.kappa, w.csw, w.bc)
+        self.ctx.load_gauge(torch.from_numpy(U).to(dev))
+        self.ctx.set_solver(w.restart, w.tol, 64)
+        self.ctx.set_sap(w.n_cycles, w.n_mr, w.prec)
+        self.ctx.set_schedule(schedule)
+        self.b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).to(dev)
+
+
+def build(name, schedule):
+    import numpy as np
+
+    from paper_1412_2629_amd import configs, inputs
+    if name == "C5":
+        out = []
+        for j, w in enumerate(configs.uneven_batch()):
+            log(f"[bench] lattice {j} {w.lattice}: generating inputs")
+            out.append(System(w, inputs.random_gauge(w.lattice, w.eps, w.gauge_seed),
+                              [inputs.gaussian_source(w.lattice, w.source_seed)], schedule))
+        return out
+    w = configs.WORKLOADS[name]
+    log(f"[bench] workload {w.name}: generating inputs")
+    U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
+    if w.nrhs > 1:   # point sources: every spin and colour at the origin
+        srcs = [inputs.point_source(w.lattice, 0, s, c) for s in range(4) for c in range(3)][:w.nrhs]
+    else:
+        srcs = [inputs.gaussian_source(w.lattice, w.source_seed)]
+    return [System(w, U, srcs, schedule)]
+
+
+def solve_all(systems, ddqcd):
+    """One step: every system of the workload to tolerance.  Returns the
+    solutions and one info record per right-hand side."""
+    if len(systems) == 1:
+        x, infos, st = systems[0].ctx.solve(systems[0].b)
+        xs = [x]
+    else:
+        xs, infos, st = ddqcd.solve_batch([s.ctx for s in systems], [s.b for s in systems])
+    if st != 0:
+        raise RuntimeError(f"solve did not converge: {infos}")
+    return xs, infos
 
 
 def main():
@@ -31,10 +88,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", default="sweeps", choices=["queue", "sweeps"],
-                    help="block-solve schedule: persistent work queue or one launch per half-sweep")
+    ap.add_argument("--schedule", default="sweeps", choices=["sweeps", "graph"],
+                    help="block-solve launches issued one by one, or replayed from a captured HIP graph")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner comparison solve")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size kernel for "
@@ -45,31 +102,12 @@ def main():
               "MI355X; multi-GPU sharding is not part of this build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_1412_2629_amd import configs, ddqcd, geometry, inputs
+    from paper_1412_2629_amd import ddqcd, geometry
 
-    w = configs.WORKLOADS[args.workload]
-    log(f"[bench] workload {w.name}: generating inputs")
-    U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
-    f = inputs.gaussian_source(w.lattice, w.source_seed)
+    systems = build(args.workload, args.schedule)
     dev = torch.device("cuda:0")
-    Ud = torch.from_numpy(U).to(dev)
-    fd = torch.from_numpy(f).to(dev)
-    ctx = ddqcd.Context(w.lattice, w.domain, w.kappa, w.csw, w.bc)
-    ctx.load_gauge(Ud)
-    ctx.set_solver(w.restart, w.tol, 64)
-    ctx.set_schedule(args.schedule)
-    del Ud
-
-    def solve(prec):
-        ctx.set_sap(w.n_cycles, w.n_mr, prec)
-        x, info, st = ctx.solve(fd)
-        if st != 0:
-            raise RuntimeError(f"solve did not converge: {info}")
-        return x, info[0]
-
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device=dev)
@@ -80,53 +118,83 @@ def main():
         del a, b
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
-        solve(w.prec)
+        solve_all(systems, ddqcd)
     torch.cuda.synchronize()
-    infos = []
+    runs = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        x, info = solve(w.prec)
-        infos.append(info)
+    for _ in range(args.steps):
+        runs.append(solve_all(systems, ddqcd))
     torch.cuda.synchronize()
     t_solve = (time.perf_counter() - t0) / args.steps
-    log(f"[bench] {args.steps} solves, {t_solve * 1e3:.2f} ms each, {infos[-1]['iters']} FGCR steps")
+    xs, infos = runs[-1]
+    iters = [i["iters"] for i in infos]
+    log(f"[bench] {args.steps} steps, {t_solve * 1e3:.2f} ms each, FGCR steps {iters}")
 
-    # true residual of the last solution, FP64 operator on the GPU
-    r = fd - ctx.apply_D(x, "f64")
-    true_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(fd))
+    # true residual of the last solutions, FP64 operator on the GPU
+    true_res = 0.0
+    for s, x in zip(systems, xs):
+        r = s.b - s.ctx.apply_D(x, "f64")
+        rr = torch.linalg.vector_norm(r.reshape(len(s.srcs), -1), dim=1)
+        bb = torch.linalg.vector_norm(s.b.reshape(len(s.srcs), -1), dim=1)
+        true_res = max(true_res, float((rr / bb).max()))
 
-    iters = infos[-1]["iters"]
-    sap_ms = sum(i["t_sap_ms"] for i in infos) / len(infos)
-    nd = w.volume // geometry.volume(w.domain)
-    per_dom = geometry.sap_flops_per_domain(w.domain, w.n_mr)
-    # one preconditioner call = n_cycles visits of every domain; it is one
-    # launch of the work-queue kernel, or 2 * n_cycles half-sweep launches
-    call_ms = sap_ms / iters
-    launches_per_call = 1 if args.schedule == "queue" else 2 * w.n_cycles
-    launch_ms = call_ms / launches_per_call
-    flops_call = per_dom["total"] * nd * w.n_cycles
-    achieved_tflops = flops_call / (call_ms * 1e-3) / 1e12
-    dslash_gflops = per_dom["dslash"] * nd * w.n_cycles / (call_ms * 1e-3) / 1e9
-    kernel = "k_sap_queue" if args.schedule == "queue" else "k_sap_lds"
+    # algorithmic SAP work of the step: every right-hand side, every
+    # preconditioner call it made (one per FGCR step)
+    per_rhs = [(s, k) for s in systems for k in range(len(s.srcs))]
+    flops = dslash = launches = 0.0
+    for (s, _), it in zip(per_rhs, iters):
+        w = s.w
+        nd = w.volume // geometry.volume(w.domain)
+        pd = geometry.sap_flops_per_domain(w.domain, w.n_mr)
+        flops += it * pd["total"] * nd * w.n_cycles
+        dslash += it * pd["dslash"] * nd * w.n_cycles
+    # launches: 2 per cycle per preconditioner call; systems of one domain
+    # shape and precision share a launch, so count the calls of the longest
+    # system per group
+    groups = {}
+    for (s, _), it in zip(per_rhs, iters):
+        key = (s.w.domain, s.w.prec)
+        groups[key] = max(groups.get(key, 0), it)
+    launches = sum(2 * systems[0].w.n_cycles * it for it in groups.values())
+    sap_ms = sum(i["t_sap_ms"] for _, inf in runs for i in inf[:1]) / len(runs)
+    launch_ms = sap_ms / launches
+    achieved_tflops = flops / (sap_ms * 1e-3) / 1e12
+    dslash_gflops = dslash / (sap_ms * 1e-3) / 1e9
 
     fp64 = None
-    if not args.no_fp64 and w.prec != "f64":
+    w0 = systems[0].w
+    if not args.no_fp64 and len(systems) == 1 and len(systems[0].srcs) == 1 and w0.prec != "f64":
         log("[bench] FP64-preconditioner comparison solve")
-        try:
-            solve("f64")
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            _, i64 = solve("f64")
-            torch.cuda.synchronize()
-            fp64 = {"fp64_sap_solve_s": round(time.perf_counter() - t1, 5), "fp64_sap_iters": i64["iters"]}
-            fp64["speedup"] = round(fp64["fp64_sap_solve_s"] / t_solve, 3)
-        except ddqcd.DDQCDError as e:
-            fp64 = {"unavailable": str(e)}
+        s = systems[0]
+        s.ctx.set_sap(w0.n_cycles, w0.n_mr, "f64")
+        solve_all(systems, ddqcd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x64, i64 = solve_all(systems, ddqcd)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        s.ctx.set_sap(w0.n_cycles, w0.n_mr, w0.prec)
+        diff = float(torch.linalg.vector_norm(xs[0] - x64[0]) / torch.linalg.vector_norm(x64[0]))
+        fp64 = {"fp64_sap_solve_s": round(t64, 5), "fp64_sap_fgcr_steps": i64[0]["iters"],
+                "mixed_solve_s": round(t_solve, 6), "mixed_fgcr_steps": iters[0],
+                "speedup_mixed_over_fp64": round(t64 / t_solve, 3),
+                "rel_diff_mixed_vs_fp64_solution": diff}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, U, f, iters)
+        cpu = cpu_baseline(systems, iters)
 
+    if args.workload == "C5":
+        wl = (f"uneven batch of {len(systems)} lattices (8 x 8^4, 8 x 12^3x24, 6 x 16^3x32, 2 x 24^3x48), "
+              f"kappa in [0.12, 0.136], c_sw 1.5, eps in [0.3, 0.6], FP16-storage SAP {w0.n_cycles}x{w0.n_mr}, "
+              f"FGCR restart {w0.restart} (f64), tol {w0.tol}, one ddqcd_solve_batch call, schedule {args.schedule}")
+        batch = len(systems)
+    else:
+        wl = (f"{w0.name}: lattice {w0.lattice}, kappa {w0.kappa}, c_sw {w0.csw}, eps {w0.eps}, "
+              f"domains {w0.domain}, SAP {w0.n_cycles} cycles x {w0.n_mr} MR ({w0.prec}), "
+              f"FGCR restart {w0.restart} (f64), tol {w0.tol}, {len(systems[0].srcs)} right-hand side(s), "
+              f"schedule {args.schedule}")
+        batch = len(systems[0].srcs)
     out = {
         "metric": METRIC,
         "value": round(t_solve, 6),
@@ -138,21 +206,18 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32+f64", "f16": "f16-storage/f32+f64"}[w.prec],
+        "dtype": {"f64": "f64", "f32": "f32+f64", "f16": "f16-storage/f32+f64"}[w0.prec],
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: lattice {w.lattice}, kappa {w.kappa}, c_sw {w.csw}, eps {w.eps}, "
-                               f"domains {w.domain}, SAP {w.n_cycles} cycles x {w.n_mr} MR ({w.prec}), "
-                               f"FGCR restart {w.restart} (f64), tol {w.tol}, schedule {args.schedule}",
-                   "global_batch": 1, "parallelism": "single GPU"},
-        "fgcr_steps": iters,
+        "config": {"workload": wl, "global_batch": batch, "parallelism": "single GPU"},
+        "fgcr_steps": iters if len(iters) > 1 else iters[0],
         "true_rel_residual": true_res,
-        "time_split_ms": {k: round(sum(i[k] for i in infos) / len(infos), 3)
+        "time_split_ms": {k: round(sum(inf[0][k] for _, inf in runs) / len(runs), 3)
                           for k in ("t_sap_ms", "t_A_ms", "t_gs_ms", "t_other_ms")},
         "sap_dslash_gflops": round(dslash_gflops, 1),
         "sap_total_tflops": round(achieved_tflops, 3),
-        "sap_call_ms": round(call_ms, 4),
+        "sap_launches_per_step": int(launches),
         "sap_launch_ms": round(launch_ms, 5),
-        "roofline": {"kernel": kernel, "bound": "alu", "achieved": round(achieved_tflops, 3),
+        "roofline": {"kernel": "k_sap_lds", "bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
                      "traffic": None},
         "mixed_vs_fp64": fp64,
@@ -161,25 +226,45 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, U, f, gpu_iters):
-    """The FP64 oracle on the host: a bounded sample of the same solve (two
-    FGCR steps with the same SAP parameters), scaled to the GPU run's number
-    of FGCR steps."""
-    import numpy as np
-
+def cpu_baseline(systems, gpu_iters):
+    """The FP64 oracle on the host, same algorithm and parameters.  One FGCR
+    step of each distinct lattice shape is timed; if the whole workload's
+    oracle solve is then estimated to fit the CPU budget it is run to the
+    tolerance and timed, otherwise the per-step times are scaled by the GPU
+    run's step counts."""
     import oracle as O
     log("[bench] cpu baseline (oracle)")
-    C = O.clover_field(w.lattice, U, w.kappa, w.csw)
-    Ci = O.clover_inverse(C)
-    nstep = 2
-    t0 = time.perf_counter()
-    O.fgcr(w.lattice, w.domain, w.bc, U, C, Ci, f, n_cycles=w.n_cycles, n_mr=w.n_mr, restart=nstep,
-           tol=1e-300, max_cycles=1)
-    dt = time.perf_counter() - t0
-    per_step = dt / nstep
-    return {"value": round(per_step * gpu_iters, 3), "unit": "s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{nstep} FGCR steps of the same solve (FP64 SAP {w.n_cycles}x{w.n_mr}, A, Gram-Schmidt, "
-                      f"one restart) in {dt:.1f} s, scaled to the GPU solve's {gpu_iters} steps"}
+    per_step = {}
+    samples = []
+    for s in systems:
+        w = s.w
+        key = (w.lattice, w.domain)
+        if key in per_step:
+            continue
+        C = O.clover_field(w.lattice, s.U, w.kappa, w.csw)
+        Ci = O.clover_inverse(C)
+        t0 = time.perf_counter()
+        O.fgcr(w.lattice, w.domain, w.bc, s.U, C, Ci, s.srcs[0], n_cycles=w.n_cycles, n_mr=w.n_mr, restart=1,
+               tol=1e-300, max_cycles=1)
+        per_step[key] = time.perf_counter() - t0
+        samples.append(f"{w.lattice}: {per_step[key]:.2f} s")
+    rhs = [s for s in systems for _ in s.srcs]
+    est = sum(per_step[(s.w.lattice, s.w.domain)] * it for s, it in zip(rhs, gpu_iters))
+    if len(rhs) == 1 and est * 1.5 <= CPU_BUDGET_S:
+        s = systems[0]
+        w = s.w
+        C = O.clover_field(w.lattice, s.U, w.kappa, w.csw)
+        Ci = O.clover_inverse(C)
+        t0 = time.perf_counter()
+        _, st, steps, rr = O.fgcr(w.lattice, w.domain, w.bc, s.U, C, Ci, s.srcs[0], n_cycles=w.n_cycles,
+                                  n_mr=w.n_mr, restart=w.restart, tol=w.tol)
+        dt = time.perf_counter() - t0
+        return {"value": round(dt, 3), "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+                "sample": f"the whole solve to {w.tol} ({steps} FGCR steps, status {st}, FP64 SAP "
+                          f"{w.n_cycles}x{w.n_mr}) on the host"}
+    return {"value": round(est, 3), "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "one FGCR step (FP64 SAP call, A, Gram-Schmidt, restart) per lattice shape ("
+                      + "; ".join(samples) + "), scaled by the GPU run's FGCR step count of every right-hand side"}
 
 
 if __name__ == "__main__":

@@ -64,7 +64,7 @@ typedef enum {
 
 typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2 } ddqcd_prec;
 
-typedef enum { DDQCD_SCHED_SWEEPS = 0, DDQCD_SCHED_QUEUE = 1 } ddqcd_schedule;
+typedef enum { DDQCD_SCHED_SWEEPS = 0, DDQCD_SCHED_QUEUE = 1, DDQCD_SCHED_GRAPH = 2 } ddqcd_schedule;
 
 typedef struct {
     int converged;        /* 1 if |b - A x| / |b| <= tol */
@@ -95,16 +95,20 @@ int ddqcd_destroy(ddqcd_t ctx);
 /* Schwarz preconditioner settings: n_cycles = I_Schwarz >= 1, n_mr = I_domain
  * >= 1 (Sec. II-D), prec = storage/arithmetic of the block solves:
  * DDQCD_FP64, DDQCD_FP32, or DDQCD_FP16 (FP16 links, clover and spinors with
- * per-domain scales, FP32 arithmetic, FP32 solution accumulator).  FP64 is
- * available for 2x2x2x2 domains only (DDQCD_ERR_GEOMETRY otherwise). */
+ * per-domain scales, FP32 arithmetic, FP32 solution accumulator).  Every
+ * precision is available for every domain shape ddqcd_create accepts. */
 int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec);
 
 /* How the block solves of one preconditioner call are scheduled.
- * DDQCD_SCHED_SWEEPS (the default, and the only one available) launches one
- * kernel per half-sweep: all domains of one colour at once, Sec. IV-B2's
- * n_domain.  DDQCD_SCHED_QUEUE, one persistent kernel taking (cycle, domain)
- * tasks from a work queue with per-domain epoch counters so that consecutive
- * half-sweeps overlap, is switched off: selecting it returns DDQCD_ERR_ARG. */
+ * DDQCD_SCHED_SWEEPS (the default) launches one kernel per colour of each
+ * half-sweep: all domains of one colour at once, Sec. IV-B2's n_domain.
+ * DDQCD_SCHED_GRAPH issues the same launches from a HIP graph captured once
+ * per set of systems and replayed for every preconditioner call (results are
+ * identical bit for bit; the launch cost is paid once).  DDQCD_SCHED_QUEUE,
+ * one persistent kernel taking (cycle, domain) tasks from a work queue with
+ * per-domain epoch counters so that consecutive half-sweeps overlap, is
+ * switched off: selecting it returns DDQCD_ERR_ARG.  In a ddqcd_solve_batch
+ * call the schedule of the first context applies. */
 int ddqcd_set_schedule(ddqcd_t ctx, int schedule);
 
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the

@@ -51,8 +51,11 @@ struct Plan {
     std::vector<Group> groups;
     SapArgs *d_args = nullptr;
     std::vector<SapArgs> h_args;
+    hipGraphExec_t graph = nullptr;   // the launches of one preconditioner call
+    int graph_cycles = -1;
     ~Plan()
     {
+        if (graph) (void)hipGraphExecDestroy(graph);
         (void)hipFree(d_args);
         for (Group &G : groups)
             for (int c = 0; c < 2; c++) (void)hipFree(G.items[c]);
@@ -85,6 +88,7 @@ struct ddqcd_ctx {
     double2 *Cs64 = nullptr;               // C_e / C_o^-1
     void *Cs32 = nullptr, *Cs16 = nullptr;
     void *t_lo_in = nullptr, *t_lo_out = nullptr;   // FP32/FP16 operands of apply_D
+    hipStream_t capture = nullptr;   // private stream on which launch graphs are captured
     std::vector<std::unique_ptr<Slot>> slots;
     std::map<std::string, std::unique_ptr<Plan>> plans;   // batch plans led by this context
     std::vector<void *> owned;
@@ -261,12 +265,66 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
     return DDQCD_OK;
 }
 
-// out_i = M eta_i for the listed systems (internal FP64 vectors); systems with
-// on[i] == 0 are skipped.  All systems share the SAP cycle count.
-int run_sap(const std::vector<Sys> &sys, const std::vector<const double2 *> &eta, const std::vector<double2 *> &out,
-            const std::vector<int> &on, hipStream_t s)
+// the launches of one preconditioner call: black domains first (colour 0),
+// then white, n_cycles times, one launch per (shape, precision) group
+hipError_t enqueue_sweeps(const Plan &plan, int n_cycles, hipStream_t s)
 {
-    ddqcd_t lead = sys[0].c;
+    for (int cyc = 0; cyc < n_cycles; cyc++)
+        for (int col = 0; col < 2; col++) {
+            Visit v;
+            v.first = cyc == 0;
+            v.faces_in = !(cyc == 0 && col == 0);
+            v.last = cyc == n_cycles - 1;
+            v.faces_out = !(v.last && col == 1);
+            v.res_out = !v.last;
+            for (const Plan::Group &G : plan.groups) {
+                hipError_t e = sap_sweep_batch(plan.d_args, G.items[col], G.nitems[col], G.shape, G.prec, v, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+    return hipSuccess;
+}
+
+int capture_graph(ddqcd_t lead, Plan &plan, int n_cycles)
+{
+    if (plan.graph) {
+        (void)hipGraphExecDestroy(plan.graph);
+        plan.graph = nullptr;
+    }
+    if (!lead->capture) HIPCHK(lead, hipStreamCreateWithFlags(&lead->capture, hipStreamNonBlocking));
+    HIPCHK(lead, hipStreamBeginCapture(lead->capture, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = enqueue_sweeps(plan, n_cycles, lead->capture);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(lead->capture, &g);   // always ends the capture
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        HIPCHK(lead, e);
+        HIPCHK(lead, e2);
+    }
+    const hipError_t e3 = hipGraphInstantiate(&plan.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(lead, e3);
+    plan.graph_cycles = n_cycles;
+    return DDQCD_OK;
+}
+
+// out_i = M eta_i for the listed systems (internal FP64 vectors); systems with
+// on[i] == 0 are left out (their out_i is not written).  All systems share the
+// SAP cycle count.
+int run_sap(const std::vector<Sys> &all, const std::vector<const double2 *> &eta_all,
+            const std::vector<double2 *> &out_all, const std::vector<int> &on, hipStream_t s)
+{
+    std::vector<Sys> sys;
+    std::vector<const double2 *> eta;
+    std::vector<double2 *> out;
+    for (size_t i = 0; i < all.size(); i++)
+        if (on[i]) {
+            sys.push_back(all[i]);
+            eta.push_back(eta_all[i]);
+            out.push_back(out_all[i]);
+        }
+    if (sys.empty()) return DDQCD_OK;
+    ddqcd_t lead = all[0].c;
     const int n_cycles = lead->n_cycles;
     Plan *plan;
     int e = build_plan(sys, plan);
@@ -288,22 +346,17 @@ int run_sap(const std::vector<Sys> &sys, const std::vector<const double2 *> &eta
         a.rho_tmp = sl->rho_tmp;
         a.links = links_for(c, c->sap_prec);
         a.cs = schur_for(c, c->sap_prec);
-        a.active = on[i];
+        a.active = 1;
     }
     HIPCHK(lead, hipMemcpyAsync(plan->d_args, plan->h_args.data(), sizeof(SapArgs) * sys.size(),
                                 hipMemcpyHostToDevice, s));
-    // black domains first (colour 0), then white, n_cycles times
-    for (int cyc = 0; cyc < n_cycles; cyc++)
-        for (int col = 0; col < 2; col++) {
-            Visit v;
-            v.first = cyc == 0;
-            v.faces_in = !(cyc == 0 && col == 0);
-            v.last = cyc == n_cycles - 1;
-            v.faces_out = !(v.last && col == 1);
-            v.res_out = !v.last;
-            for (const Plan::Group &G : plan->groups)
-                HIPCHK(lead, sap_sweep_batch(plan->d_args, G.items[col], G.nitems[col], G.shape, G.prec, v, s));
-        }
+    if (lead->schedule == DDQCD_SCHED_GRAPH) {
+        if (!plan->graph || plan->graph_cycles != n_cycles)
+            if ((e = capture_graph(lead, *plan, n_cycles))) return e;
+        HIPCHK(lead, hipGraphLaunch(plan->graph, s));
+        return DDQCD_OK;
+    }
+    HIPCHK(lead, enqueue_sweeps(*plan, n_cycles, s));
     return DDQCD_OK;
 }
 
@@ -677,6 +730,7 @@ int ddqcd_destroy(ddqcd_t c)
 {
     if (!c) return DDQCD_OK;
     c->plans.clear();
+    if (c->capture) (void)hipStreamDestroy(c->capture);
     for (void *p : c->owned) (void)hipFree(p);
     delete c;
     return DDQCD_OK;
@@ -688,7 +742,7 @@ int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec)
     if (n_cycles < 1 || n_mr < 1 || n_cycles > 1000 || n_mr > 1000) return fail(c, DDQCD_ERR_ARG, "bad SAP iteration counts");
     if (prec != DDQCD_FP64 && prec != DDQCD_FP32 && prec != DDQCD_FP16) return fail(c, DDQCD_ERR_ARG, "bad precision");
     if (!sap_prec_supported(c->g.b, prec))
-        return fail(c, DDQCD_ERR_GEOMETRY, "FP64 block solves are available for 2x2x2x2 domains only");
+        return fail(c, DDQCD_ERR_GEOMETRY, "no block-solve kernel for this domain shape and precision");
     c->n_cycles = n_cycles;
     c->n_mr = n_mr;
     c->sap_prec = prec;
@@ -698,7 +752,8 @@ int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec)
 int ddqcd_set_schedule(ddqcd_t c, int schedule)
 {
     if (!c) return DDQCD_ERR_ARG;
-    if (schedule != DDQCD_SCHED_SWEEPS && schedule != DDQCD_SCHED_QUEUE) return fail(c, DDQCD_ERR_ARG, "bad schedule");
+    if (schedule != DDQCD_SCHED_SWEEPS && schedule != DDQCD_SCHED_QUEUE && schedule != DDQCD_SCHED_GRAPH)
+        return fail(c, DDQCD_ERR_ARG, "bad schedule");
     if (schedule == DDQCD_SCHED_QUEUE)
         return fail(c, DDQCD_ERR_ARG, "the work-queue schedule is switched off: it stalled on the device and its cause "
                                       "is not established");

@@ -149,7 +149,7 @@ template <typename T> __device__ __forceinline__ T maxabs12(const cx<T> a[12])
 
 template <class Sh, int MU, typename T, typename G, int NLC>
 __device__ __forceinline__ void dom_hop(const cx<T> (*v)[Sh::VH], const int l[4], long lbase, int loc,
-                                        const v2<G> *links, cx<T> acc[12])
+                                        const v2<G> *links, cx<T> acc[12], T scale = T(1))
 {
     constexpr int VD = Sh::VD;
     int n[4] = {l[0], l[1], l[2], l[3]};
@@ -162,7 +162,7 @@ __device__ __forceinline__ void dom_hop(const cx<T> (*v)[Sh::VH], const int l[4]
         proj<MU, -1>(s, h);
         su3<T> U = ld_link<T, G, NLC>(links, lbase + (long)MU * NLC * VD + loc, VD);
         su3_mul(U, h, uh);
-        recon_acc<MU, -1>(acc, uh, T(1));
+        recon_acc<MU, -1>(acc, uh, scale);
     }
     if (l[MU] > 0) {
         n[MU] = l[MU] - 1;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void dom_hop(const cx<T> (*v)[Sh::VH], const int l[4]
         proj<MU, +1>(s, h);
         su3<T> U = ld_link<T, G, NLC>(links, lbase + (long)MU * NLC * VD + nloc, VD);
         su3_dag_mul(U, h, uh);
-        recon_acc<MU, +1>(acc, uh, T(1));
+        recon_acc<MU, +1>(acc, uh, scale);
     }
 }
 
@@ -187,6 +187,37 @@ __device__ __forceinline__ void dom_hops(const cx<T> (*v)[Sh::VH], const int l[4
     dom_hop<Sh, 1, T, G, NLC>(v, l, lbase, loc, links, acc);
     dom_hop<Sh, 2, T, G, NLC>(v, l, lbase, loc, links, acc);
     dom_hop<Sh, 3, T, G, NLC>(v, l, lbase, loc, links, acc);
+}
+
+// A uniform pointer the compiler must treat as unknown from here on: the
+// addresses derived from it are formed at their use instead of being
+// precomputed and held in registers across loops.
+template <typename P> __device__ __forceinline__ P opaque(P p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// acc (= 0 first if ZERO) += scale * (in-domain hops), directions visited in
+// a loop that is not unrolled: one direction's temporaries live at a time
+// (fewer registers)
+template <class Sh, typename T, typename G, int NLC, bool ZERO>
+__device__ __forceinline__ void dom_hops_rolled(const cx<T> (*v)[Sh::VH], const int l[4], long lbase, int loc,
+                                                const v2<G> *links, cx<T> acc[12], T scale)
+{
+    if constexpr (ZERO)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = czero<T>();
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++) {
+        const v2<G> *lk = opaque(links);
+        switch (mu) {
+            case 0: dom_hop<Sh, 0, T, G, NLC>(v, l, lbase, loc, lk, acc, scale); break;
+            case 1: dom_hop<Sh, 1, T, G, NLC>(v, l, lbase, loc, lk, acc, scale); break;
+            case 2: dom_hop<Sh, 2, T, G, NLC>(v, l, lbase, loc, lk, acc, scale); break;
+            default: dom_hop<Sh, 3, T, G, NLC>(v, l, lbase, loc, lk, acc, scale); break;
+        }
+    }
 }
 
 // ---- boundary terms --------------------------------------------------------
@@ -482,12 +513,16 @@ __device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12
     clover_block_reg<T, G>(cl + 18, in + 6, out + 6);
 }
 
-template <class Sh, typename SS, typename G, bool SCALED>
+// T: arithmetic; SS: storage of the block residual and faces; PS: storage of
+// the solution accumulator; G: links and clover; NLC: complex numbers stored
+// per link (6: two rows, 9: full).  LINK_LDS stages the domain's links into
+// LDS (else they are read from global memory at each use); CL_REG keeps the
+// site's clover block in registers (else it is read from global memory).
+template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS, bool CL_REG>
 __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
 {
-    using T = float;
-    constexpr int VD = Sh::VD, VH = Sh::VH, NLC = 6;
-    __shared__ v2<G> slink[4 * NLC * VD];   // [mu][6][VD]: rows 0-1 of U_mu(x)
+    constexpr int VD = Sh::VD, VH = Sh::VH;
+    __shared__ v2<G> slink[LINK_LDS ? 4 * NLC * VD : 1];   // [mu][NLC][VD]
     __shared__ cx<T> she[12][VH];
     __shared__ cx<T> sho[12][VH];
     __shared__ T red[VD >= 64 ? 3 * (VD / 64) : 3 * VD];
@@ -510,14 +545,27 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     const long sbase = (long)d * 12 * VD + loc;
 
     // ---- stage the links into LDS, the site's clover block into registers
-    {
+    const v2<G> *links = slink;
+    long lbase = 0;
+    if constexpr (LINK_LDS) {
         const long lb = (long)d * 4 * NLC * VD + loc;
 #pragma unroll
         for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = glinks[lb + (long)q * VD];
+    } else {
+        links = glinks;
+        lbase = (long)d * 4 * NLC * VD;
     }
-    v2<G> cl[36];
+    const long cbase = (long)d * 36 * VD + loc;
+    v2<G> cl[CL_REG ? 36 : 1];
+    if constexpr (CL_REG) {
 #pragma unroll
-    for (int q = 0; q < 36; q++) cl[q] = cs[((long)d * 36 + q) * VD + loc];
+        for (int q = 0; q < 36; q++) cl[q] = cs[cbase + (long)q * VD];
+    }
+    // this site's clover block (C_e on even sites, C_o^-1 on odd sites) times in
+    auto clover = [&](const cx<T> in[12], cx<T> out[12]) {
+        if constexpr (CL_REG) clover_reg<T, G>(cl, in, out);
+        else clover_apply<T, G>(cs, cbase, VD, in, out);
+    };
 
     // A: even sites x (MR solution), odd sites rho_o then delta_o
     cx<T> A[12], P[12];
@@ -542,7 +590,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 
     // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0
     if (par == 1) {
-        clover_reg<T, G>(cl, A, P);
+        clover(A, P);
 #pragma unroll
         for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
     }
@@ -550,7 +598,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     // the even-site MR residual r lives in its own slot of she for the whole
     // solve (fewer live registers); x stays in the registers of A
     if (par == 0) {
-        dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, P);
+        dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, P);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             she[k][hi] = A[k] + scal(T(0.5), P[k]);
@@ -561,7 +609,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     // ---- minimal residual on the Schur complement
 #pragma unroll 1
     for (int it = 0; it < a.n_mr; it++) {
-        if constexpr (sizeof(v2<G>) == 4) {
+        if constexpr (CL_REG && sizeof(v2<G>) == 4) {
             // keep the clover block in its 16-bit storage form: stops the
             // compiler from hoisting its widening out of the loop, which would
             // double the registers it occupies
@@ -571,10 +619,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         __syncthreads();
         if (par == 1) {
             cx<T> t[12];
-            dom_hops<Sh, T, G, NLC>(she, l, 0, loc, slink, t);
+            dom_hops<Sh, T, G, NLC>(she, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) t[k] = scal(T(-0.5), t[k]);   // D_oe r
-            clover_reg<T, G>(cl, t, P);                                // C_o^-1 D_oe r
+            clover(t, P);                                // C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
         }
@@ -582,10 +630,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         T dots[3] = {0, 0, 0};
         if (par == 0) {
             cx<T> t[12], rr[12];
-            dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, t);
+            dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) rr[k] = she[k][hi];
-            clover_reg<T, G>(cl, rr, P);                               // C_e r
+            clover(rr, P);                               // C_e r
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 P[k] = P[k] + scal(T(0.5), t[k]);
@@ -614,21 +662,21 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     __syncthreads();
     if (par == 1) {
         cx<T> t[12];
-        dom_hops<Sh, T, G, NLC>(sho, l, 0, loc, slink, t);
+        dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
-        clover_reg<T, G>(cl, t, A);
+        clover(t, A);
     }
 
     // ---- epilogue
     {
-        const v2<float> *psi_in = (const v2<float> *)a.psi;
-        v2<float> *psi_out = (v2<float> *)a.psi;
+        const v2<PS> *psi_in = (const v2<PS> *)a.psi;
+        v2<PS> *psi_out = (v2<PS> *)a.psi;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            cx<T> ps = f.first ? A[k] : ld<T, float>(psi_in, sbase + (long)k * VD) + A[k];
+            cx<T> ps = f.first ? A[k] : ld<T, PS>(psi_in, sbase + (long)k * VD) + A[k];
             if (f.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
-            else st<T, float>(psi_out, sbase + (long)k * VD, ps);
+            else st<T, PS>(psi_out, sbase + (long)k * VD, ps);
         }
     }
     if (f.res_out) {
@@ -662,6 +710,159 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 }
 
 
+// ---- the FP64 block solve for domains of 256 and more sites -------------------
+//
+// The same schedule as lds_block_solve (one workgroup per domain, one thread
+// per site, Schur complement MR on the even sites), laid out for FP64's
+// register cost: the even-site r and x live in LDS, links and clover blocks
+// are read from global memory at each use (they stay in the L1/L2 caches
+// within a block solve), the odd-site right-hand side is parked in global
+// memory until the reconstruction, and the hop directions are visited in a
+// loop, so no thread holds more than two 12-component vectors at a time.
+
+template <class Sh>
+__device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, const Visit f)
+{
+    using T = double;
+    using G = double;
+    constexpr int VD = Sh::VD, VH = Sh::VH, NLC = 9;
+    __shared__ cx<T> she[12][VH];   // even sites: MR residual r
+    __shared__ cx<T> sho[12][VH];   // odd sites: C_o^-1 D_oe r
+    __shared__ cx<T> shx[12][VH];   // even sites: MR solution x
+    __shared__ T red[VD >= 64 ? 3 * (VD / 64) : 3 * VD];
+
+    const int loc = threadIdx.x;
+    const int par = loc >= VH;
+    const int hi = loc - par * VH;
+    int l[4];
+    Sh::coords(loc, l);
+    int D[4];
+    {
+        int r = d;
+        D[0] = r % a.g.n[0]; r /= a.g.n[0];
+        D[1] = r % a.g.n[1]; r /= a.g.n[1];
+        D[2] = r % a.g.n[2];
+        D[3] = r / a.g.n[2];
+    }
+    const v2<G> *links = (const v2<G> *)a.links;
+    const long lbase = (long)d * 4 * NLC * VD;
+    const v2<G> *cs = (const v2<G> *)a.cs;
+    const long cbase = (long)d * 36 * VD + loc;
+    v2<T> *rho_g = (v2<T> *)a.rho_tmp;
+    const long sbase = (long)d * 12 * VD + loc;
+
+    // ---- the block right-hand side rho
+    cx<T> A[12], P[12];
+    if (f.first) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
+    } else if (par == 0) {
+        const v2<T> *res = (const v2<T> *)a.res;
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = ld<T, T>(res, ((long)d * 12 + k) * VH + hi);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = czero<T>();
+    }
+    if (f.faces_in) {
+        gather_face<Sh, 0, T, T, G, NLC, false>(a, D, d, l, loc, A);
+        gather_face<Sh, 1, T, T, G, NLC, false>(a, D, d, l, loc, A);
+        gather_face<Sh, 2, T, T, G, NLC, false>(a, D, d, l, loc, A);
+        gather_face<Sh, 3, T, T, G, NLC, false>(a, D, d, l, loc, A);
+    }
+
+    // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0
+    if (par == 1) {
+        clover_apply<T, G>(opaque(cs), cbase, VD, A, P);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            sho[k][hi] = P[k];
+            st<T, T>(rho_g, ((long)d * 12 + k) * VH + hi, A[k]);
+        }
+    }
+    __syncthreads();
+    if (par == 0) {
+        dom_hops_rolled<Sh, T, G, NLC, false>(sho, l, lbase, loc, links, A, T(0.5));
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            she[k][hi] = A[k];
+            shx[k][hi] = czero<T>();
+        }
+    }
+
+    // ---- minimal residual on the Schur complement
+#pragma unroll 1
+    for (int it = 0; it < a.n_mr; it++) {
+        __syncthreads();
+        if (par == 1) {
+            dom_hops_rolled<Sh, T, G, NLC, true>(she, l, lbase, loc, links, P, T(-0.5));   // D_oe r
+            clover_apply<T, G>(opaque(cs), cbase, VD, P, A);                                       // C_o^-1 D_oe r
+#pragma unroll
+            for (int k = 0; k < 12; k++) sho[k][hi] = A[k];
+        }
+        __syncthreads();
+        T dots[3] = {0, 0, 0};
+        if (par == 0) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) A[k] = she[k][hi];
+            clover_apply<T, G>(opaque(cs), cbase, VD, A, P);                                       // C_e r
+            dom_hops_rolled<Sh, T, G, NLC, false>(sho, l, lbase, loc, links, P, T(0.5));   // - D_eo C_o^-1 D_oe r
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<T> rk = she[k][hi];
+                dots[0] += P[k].r * rk.r + P[k].i * rk.i;
+                dots[1] += P[k].r * rk.i - P[k].i * rk.r;
+                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+            }
+        }
+        block_sum<VD, T, 3>(dots, red);
+        if (par == 0) {
+            const cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<T> rk = she[k][hi];
+                shx[k][hi] = shx[k][hi] + alpha * rk;
+                she[k][hi] = rk - alpha * P[k];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- delta: x on even sites, C_o^-1 (rho_o - D_oe x) on odd sites
+    if (par == 1) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) P[k] = ld<T, T>(rho_g, ((long)d * 12 + k) * VH + hi);
+        dom_hops_rolled<Sh, T, G, NLC, false>(shx, l, lbase, loc, links, P, T(0.5));
+        clover_apply<T, G>(opaque(cs), cbase, VD, P, A);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = shx[k][hi];
+    }
+
+    // ---- epilogue: psi += delta, stored residual, boundary terms
+    {
+        const v2<T> *psi_in = (const v2<T> *)a.psi;
+        v2<T> *psi_out = (v2<T> *)a.psi;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const cx<T> ps = f.first ? A[k] : ld<T, T>(psi_in, sbase + (long)k * VD) + A[k];
+            if (f.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
+            else st<T, T>(psi_out, sbase + (long)k * VD, ps);
+        }
+    }
+    if (f.res_out && par == 0) {
+        v2<T> *res = (v2<T> *)a.res;
+#pragma unroll
+        for (int k = 0; k < 12; k++) st<T, T>(res, ((long)d * 12 + k) * VH + hi, she[k][hi]);
+    }
+    if (f.faces_out) {
+        write_face<Sh, 0, T, T, G, NLC>(a, d, l, loc, A, T(1));
+        write_face<Sh, 1, T, T, G, NLC>(a, d, l, loc, A, T(1));
+        write_face<Sh, 2, T, T, G, NLC>(a, d, l, loc, A, T(1));
+        write_face<Sh, 3, T, T, G, NLC>(a, d, l, loc, A, T(1));
+    }
+}
+
 // ---- batched half-sweeps ------------------------------------------------------
 //
 // One launch covers one colour of one half-sweep for many systems (right-hand
@@ -669,14 +870,24 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 // domain) and that system's arguments.  Items with system < 0 are padding;
 // systems with active == 0 (already converged) are skipped.
 
-template <class Sh, typename SS, typename G, bool SCALED>
+template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS, bool CL_REG>
 __global__ __launch_bounds__(Sh::VD) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
 {
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;
     const SapArgs a = args[it.x];
     if (!a.active) return;
-    lds_block_solve<Sh, SS, G, SCALED>(a, it.y, v);
+    lds_block_solve<Sh, T, SS, PS, G, NLC, SCALED, LINK_LDS, CL_REG>(a, it.y, v);
+}
+
+template <class Sh>
+__global__ __launch_bounds__(Sh::VD) void k_sap_f64(const SapArgs *args, const int2 *items, Visit v)
+{
+    const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;
+    const SapArgs a = args[it.x];
+    if (!a.active) return;
+    f64_block_solve<Sh>(a, it.y, v);
 }
 
 template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool RHO_LDS>
@@ -771,7 +982,7 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
         if (!__builtin_amdgcn_readfirstlane(ok_s)) continue;
         __atomic_thread_fence(__ATOMIC_ACQUIRE);   // system scope: see the neighbours' results
         const int last = s == q.n_cycles - 1;
-        lds_block_solve<Sh, SS, G, SCALED>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
+        lds_block_solve<Sh, float, SS, float, G, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
         __threadfence_system();                     // this block's results reach memory ...
         __syncthreads();
         if (threadIdx.x == 0)                       // ... before its epoch moves on
@@ -792,13 +1003,17 @@ __global__ void k_epoch_reset(int *epoch, int nd, int *error)
 template <class Sh>
 static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
 {
-    if (prec == P64)
+    if (prec == P64 && Sh::VD == 16)
         hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
                            dim3(Sh::VH), 0, s, args, items, v);
+    else if (prec == P64)
+        hipLaunchKernelGGL((k_sap_f64<Sh>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
     else if (prec == P32)
-        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, false>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
+        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, float, float, 6, false, true, true>), dim3(nitems),
+                           dim3(Sh::VD), 0, s, args, items, v);
     else
-        hipLaunchKernelGGL((k_sap_lds<Sh, half_t, half_t, true>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
+        hipLaunchKernelGGL((k_sap_lds<Sh, float, half_t, float, half_t, 6, true, true, true>), dim3(nitems),
+                           dim3(Sh::VD), 0, s, args, items, v);
     return hipGetLastError();
 }
 
@@ -812,10 +1027,7 @@ int sap_shape_id(const int b[4])
 
 bool sap_shape_supported(const int b[4]) { return sap_shape_id(b) >= 0; }
 
-// FP64 block solves are built for 2^4 domains only: on larger domains the
-// FP64 instantiation spills registers to scratch memory, and that variant is
-// switched off until it is shown correct on the device.
-bool sap_prec_supported(const int b[4], int prec) { return sap_shape_id(b) >= 0 && (prec != P64 || sap_shape_id(b) == 0); }
+bool sap_prec_supported(const int b[4], int prec) { return sap_shape_id(b) >= 0 && prec >= P64 && prec <= P16; }
 
 long sap_face_sites(const int b[4])
 {
@@ -860,7 +1072,6 @@ hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, i
                            hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
-    if (prec == P64 && shape != 0) return hipErrorInvalidValue;
     switch (shape) {
         case 0: return launch_batch<Shape<2, 2, 2, 2>>(args, items, nitems, prec, v, s);
         case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, v, s);

@@ -15,7 +15,7 @@ OK, ERR_ARG, ERR_GEOMETRY, ERR_STATE, ERR_DEVICE, ERR_NOMEM, ERR_NOT_CONVERGED, 
 FP64, FP32, FP16 = 0, 1, 2
 PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
 
-SCHED_SWEEPS, SCHED_QUEUE = 0, 1
+SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_last_error",
@@ -121,8 +121,9 @@ class Context:
         self._check(lib().ddqcd_set_sap(self._h, n_cycles, n_mr, PREC[prec]), "set_sap")
 
     def set_schedule(self, schedule):
-        """"sweeps" (one launch per half-sweep) or "queue" (persistent work-queue kernel)."""
-        mode = {"sweeps": SCHED_SWEEPS, "queue": SCHED_QUEUE}.get(schedule, schedule)
+        """"sweeps" (one launch per colour of a half-sweep), "graph" (the same launches replayed
+        from a captured HIP graph) or "queue" (persistent work-queue kernel, switched off)."""
+        mode = {"sweeps": SCHED_SWEEPS, "queue": SCHED_QUEUE, "graph": SCHED_GRAPH}.get(schedule, schedule)
         self._check(lib().ddqcd_set_schedule(self._h, mode), "set_schedule")
 
     def set_solver(self, restart=16, tol=1e-10, max_cycles=64):

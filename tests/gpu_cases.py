@@ -50,10 +50,6 @@ class Case:
     def source(self, seed=None):
         return inputs.gaussian_source(self.L, self.seed + 1 if seed is None else seed)
 
-    @property
-    def fp64_sap(self):
-        return self.b == (2, 2, 2, 2)
-
     def context(self, prec=None):
         from paper_1412_2629_amd import ddqcd
         ctx = ddqcd.Context(self.L, self.b, self.kappa, self.csw, BC)
@@ -62,12 +58,6 @@ class Case:
             ctx.set_sap(self.n_cycles, self.n_mr, prec)
         return ctx
 
-
-# FP64 block solves run on 2^4 domains only: on larger domains the FP64
-# instantiation of the block-solve kernel spills registers to scratch memory;
-# that variant faulted once on the device and stays switched off (the library
-# returns DDQCD_ERR_GEOMETRY for it) until its cause is shown.
-FP64_SAP_SKIP = "FP64 block solves on >= 256-site domains are switched off in the library"
 
 
 SMALL = [

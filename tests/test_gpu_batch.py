@@ -111,3 +111,41 @@ def test_solve_batch_rejects_mixed_settings():
     with pytest.raises(ddqcd.DDQCDError) as e:
         ddqcd.solve_batch([a, b], [dev(f_a), dev(f_b)])
     assert e.value.status == ddqcd.ERR_ARG
+
+
+@pytest.mark.parametrize("ci,prec", [(0, "f64"), (2, "f16"), (2, "f64"), (3, "f32")], ids=lambda v: str(v))
+def test_graph_schedule_replays_match_eager(ci, prec):
+    """The captured launch graph gives the eager launches' result bit for bit,
+    on every replay, with other (eager) GPU work between the replays."""
+    case = SMALL[ci]
+    ctx = case.context(prec)
+    etas = [case.source(80 + k) for k in range(3)]
+    eager = [host(ctx.sap(dev(e))) for e in etas]
+    ctx.set_schedule("graph")
+    for rep in range(3):
+        for k, e in enumerate(etas):
+            got = host(ctx.sap(dev(e)))
+            assert np.array_equal(got, eager[k]), (rep, k)
+            ctx.apply_D(dev(e), "f64")   # eager work between replays
+    f = case.source(90)
+    x_g, info_g, st_g = ctx.solve(dev(f))
+    ctx.set_schedule("sweeps")
+    x_s, info_s, st_s = ctx.solve(dev(f))
+    assert st_g == st_s == 0 and info_g[0]["iters"] == info_s[0]["iters"]
+    assert np.array_equal(host(x_g), host(x_s))
+
+
+def test_graph_schedule_batch():
+    from paper_1412_2629_amd import ddqcd
+    a = SMALL[2].context()
+    a.set_sap(4, 5, "f16")
+    b = SMALL[3].context()
+    b.set_sap(4, 5, "f32")
+    fs = [dev(SMALL[2].source(91)), dev(SMALL[3].source(92)), dev(SMALL[2].source(93))]
+    xs_s, inf_s, st_s = ddqcd.solve_batch([a, b, a], fs)
+    a.set_schedule("graph")
+    for _ in range(2):
+        xs_g, inf_g, st_g = ddqcd.solve_batch([a, b, a], fs)
+        assert st_g == st_s == 0
+        for xg, xs in zip(xs_g, xs_s):
+            assert np.array_equal(host(xg), host(xs))

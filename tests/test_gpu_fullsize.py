@@ -70,16 +70,18 @@ def test_apply_D_sampled(name, oracle):
         assert err <= A_TOL[prec]
 
 
-@pytest.mark.parametrize("name", ["C2", "C3"])
-def test_solve_true_residual(name, oracle):
+@pytest.mark.parametrize("name,prec", [("C2", None), ("C3", None), ("C2", "f64")])
+def test_solve_true_residual(name, prec, oracle):
     w, U, f = fields(name)
     ctx = context(w, U)
+    if prec is not None:   # the plain FP64 preconditioner on the same domains
+        ctx.set_sap(w.n_cycles, w.n_mr, prec)
     x, info, st = ctx.solve(dev(f))
     assert st == 0, info
     x = host(x)
     Ax = oracle.apply_A_sites(w.lattice, w.bc, U, w.kappa, w.csw, x, np.arange(w.volume, dtype=np.int64))
     true_res = rel(Ax, f)
-    print(f"{name}: {info[0]['iters']} FGCR steps, true residual (oracle A) {true_res:.3e}, "
+    print(f"{name} {prec or w.prec}: {info[0]['iters']} FGCR steps, true residual (oracle A) {true_res:.3e}, "
           f"reported {info[0]['rel_residual']:.3e}")
     assert true_res <= 1e-10
     assert abs(true_res - info[0]["rel_residual"]) <= 1e-12

@@ -10,7 +10,7 @@ Tolerances (normwise relative errors):
 import numpy as np
 import pytest
 
-from tests.gpu_cases import BC, FP64_SAP_SKIP, SMALL, Case, dev, host, rel
+from tests.gpu_cases import BC, SMALL, Case, dev, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -49,8 +49,6 @@ def test_apply_D_batched_rhs(oracle):
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
 def test_sap_fp64(case, oracle):
-    if not case.fp64_sap:
-        pytest.skip(FP64_SAP_SKIP)
     eta = case.source(5)
     want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
     ctx = case.context("f64")
@@ -111,18 +109,16 @@ def test_queue_equals_sweeps_bitwise(case, prec):
 @pytest.mark.parametrize("case", SMALL[:3], ids=repr)
 def test_sap_homogeneous(case):
     eta = case.source(6)
-    ctx = case.context("f64" if case.fp64_sap else "f32")
+    ctx = case.context("f64")
     s = 0.3 + 1.7j
     m1 = host(ctx.sap(dev(eta)))
     m2 = host(ctx.sap(dev(s * eta)))
-    assert rel(m2, s * m1) < (1e-13 if case.fp64_sap else 1e-5)
+    assert rel(m2, s * m1) < 1e-13
 
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_solve(case, prec, oracle):
-    if prec == "f64" and not case.fp64_sap:
-        pytest.skip(FP64_SAP_SKIP)
     f = case.source(3)
     x_or, st, steps, rr = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
                                       n_mr=case.n_mr, restart=16, tol=1e-12)
@@ -172,14 +168,6 @@ def test_queue_schedule_switched_off():
         ctx.set_schedule("queue")
     assert e.value.status == ddqcd.ERR_ARG
     ctx.set_schedule("sweeps")
-
-
-def test_fp64_sap_switched_off_on_large_domains():
-    from paper_1412_2629_amd import ddqcd
-    ctx = SMALL[2].context()
-    with pytest.raises(ddqcd.DDQCDError) as e:
-        ctx.set_sap(4, 5, "f64")
-    assert e.value.status == ddqcd.ERR_GEOMETRY
 
 
 def test_solve_edge_cases():
