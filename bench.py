@@ -26,6 +26,14 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32
 HBM_PEAK_GBS = 8000.0
 CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 
+# HBM bytes per half-sweep launch of the block-solve kernel, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes calibrated against a plain device copy
+# (profiles/k_sap_lds_16x16x16x32_f32.md).  They hold for the kernel sources
+# they were taken on, identified by a hash; after any change to those sources
+# the figure is reported as null until it is measured again.
+KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
+MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.45e6, "sources": "df8906bf2d8dc378"}}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -81,6 +89,15 @@ def solve_all(systems, ddqcd):
     if st != 0:
         raise RuntimeError(f"solve did not converge: {infos}")
     return xs, infos
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -161,6 +178,11 @@ def main():
     achieved_tflops = flops / (sap_ms * 1e-3) / 1e12
     dslash_gflops = dslash / (sap_ms * 1e-3) / 1e9
 
+    traffic = None
+    m = MEASURED_TRAFFIC.get(args.workload)
+    if m and m["sources"] == kernel_sources_hash():
+        traffic = m["bytes_per_launch"]
+
     fp64 = None
     w0 = systems[0].w
     if not args.no_fp64 and len(systems) == 1 and len(systems[0].srcs) == 1 and w0.prec != "f64":
@@ -219,7 +241,7 @@ def main():
         "sap_launch_ms": round(launch_ms, 5),
         "roofline": {"kernel": "k_sap_lds", "bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
-                     "traffic": None},
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)"},
         "mixed_vs_fp64": fp64,
         "cpu_baseline": cpu,
     }
