@@ -57,16 +57,26 @@ class System:
         self.b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).to(dev)
 
 
-def build(name, schedule):
-    import numpy as np
+def build(name, schedule, tune=False):
+    import dataclasses
 
-    from paper_1412_2629_amd import configs, inputs
+    import numpy as np
+    import torch
+
+    from paper_1412_2629_amd import configs, ddqcd, inputs
     if name == "C5":
         out = []
         for j, w in enumerate(configs.uneven_batch()):
             log(f"[bench] lattice {j} {w.lattice}: generating inputs")
-            out.append(System(w, inputs.random_gauge(w.lattice, w.eps, w.gauge_seed),
-                              [inputs.gaussian_source(w.lattice, w.source_seed)], schedule))
+            U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
+            src = inputs.gaussian_source(w.lattice, w.source_seed)
+            if tune:   # the domain shape this lattice solves fastest with (untimed set-up)
+                dom, ms = ddqcd.tune_domain(w.lattice, w.kappa, w.csw, torch.from_numpy(U).cuda(),
+                                            torch.from_numpy(src).cuda(), w.prec, w.n_cycles, w.n_mr, w.restart,
+                                            w.tol, 64, w.bc)
+                log(f"[bench] lattice {j}: domain {dom}" + (f" ({ms:.1f} ms)" if ms >= 0 else " (only fit)"))
+                w = dataclasses.replace(w, domain=dom)
+            out.append(System(w, U, [src], schedule))
         return out
     w = configs.WORKLOADS[name]
     log(f"[bench] workload {w.name}: generating inputs")
@@ -110,6 +120,8 @@ def main():
     ap.add_argument("--schedule", default="sweeps", choices=["sweeps", "graph"],
                     help="block-solve launches issued one by one, or replayed from a captured HIP graph")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner comparison solve")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uneven batch: keep the listed domain shapes instead of autotuning them per lattice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size kernel for "
                          "calibrating profiler byte counters)")
@@ -123,7 +135,9 @@ def main():
 
     from paper_1412_2629_amd import ddqcd, geometry
 
-    systems = build(args.workload, args.schedule)
+    t_tune = time.perf_counter()
+    systems = build(args.workload, args.schedule, tune=not args.no_tune)
+    t_tune = time.perf_counter() - t_tune
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -207,7 +221,10 @@ def main():
         cpu = cpu_baseline(systems, iters)
 
     if args.workload == "C5":
+        doms = sorted({(s.w.lattice, s.w.domain) for s in systems})
         wl = (f"uneven batch of {len(systems)} lattices (8 x 8^4, 8 x 12^3x24, 6 x 16^3x32, 2 x 24^3x48), "
+              f"domains {'autotuned' if not args.no_tune else 'as listed'} "
+              f"{[(l, d, sum(1 for s in systems if (s.w.lattice, s.w.domain) == (l, d))) for l, d in doms]}, "
               f"kappa in [0.12, 0.136], c_sw 1.5, eps in [0.3, 0.6], FP16-storage SAP {w0.n_cycles}x{w0.n_mr}, "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, one ddqcd_solve_batch call, schedule {args.schedule}")
         batch = len(systems)
@@ -239,6 +256,7 @@ def main():
         "sap_total_tflops": round(achieved_tflops, 3),
         "sap_launches_per_step": int(launches),
         "sap_launch_ms": round(launch_ms, 5),
+        "setup_s": round(t_tune, 3),
         "roofline": {"kernel": "k_sap_lds", "bound": "alu", "achieved": round(achieved_tflops, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)"},

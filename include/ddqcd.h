@@ -157,6 +157,25 @@ int ddqcd_solve(ddqcd_t ctx, double *x, const double *b, int nrhs, int x_is_gues
 int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double *const *b, int x_is_guess,
                       ddqcd_info *info, void *stream);
 
+/* Picks a domain shape for a lattice.  The domain size trades the number of
+ * independent block solves per half-sweep (Sec. IV-B2's n_domain, the
+ * parallelism) against the strength of the preconditioner (larger blocks,
+ * fewer outer iterations; Sec. II-D, IV-C), and the best trade depends on the
+ * lattice and the gauge field, so it is measured: for every compiled
+ * block-solve shape that tiles the lattice with an even number (>= 2) of
+ * domains in each direction, a context is created, U loaded (device pointer,
+ * canonical layout) and b solved (device pointer, canonical layout, one
+ * right-hand side) twice with the given settings; the second solve is timed.
+ * The fastest shape that converged is written to domain_out and its solve time
+ * in milliseconds to ms_out (optional).  If only one shape fits, it is
+ * returned without timing and ms_out is set to -1.  Allocates and frees its
+ * own device memory (one solution vector and the candidates' contexts, one at
+ * a time).  Returns DDQCD_ERR_GEOMETRY if no compiled shape fits, otherwise
+ * the error of the last failing candidate if none converged. */
+int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
+                      const double *b, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
+                      int domain_out[4], double *ms_out, void *stream);
+
 /* Text of the last error on this context (never NULL; "" if none). */
 const char *ddqcd_last_error(ddqcd_t ctx);
 

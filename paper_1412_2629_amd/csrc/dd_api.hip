@@ -237,24 +237,33 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
         Plan::Group &G = plan->groups.back();
         G.shape = gk[gi].first;
         G.prec = gk[gi].second;
+        const int ndw = sap_domains_per_workgroup(G.shape, G.prec);
         for (int col = 0; col < 2; col++) {
-            // one list per XCD; the items of one (context, domain) share a list
-            std::vector<std::vector<int2>> lane(N_XCD);
+            // runs of ndw domains of one system (one workgroup each), one list
+            // of runs per XCD; the runs of one (context, domain run) share a list
+            std::vector<std::vector<std::vector<int2>>> lane(N_XCD);
             std::map<std::pair<ddqcd_t, int>, int> key_lane;
             int next = 0;
-            for (int si : members[gi])
-                for (int d : sys[si].c->dom_host[col]) {
-                    const auto kd = std::make_pair(sys[si].c, d);
+            for (int si : members[gi]) {
+                const std::vector<int> &doms = sys[si].c->dom_host[col];
+                if (doms.size() % ndw)
+                    return fail(lead, DDQCD_ERR_GEOMETRY, "domain count per colour not a multiple of the workgroup's");
+                for (size_t r = 0; r * ndw < doms.size(); r++) {
+                    const auto kd = std::make_pair(sys[si].c, (int)r);
                     auto f = key_lane.find(kd);
-                    int ln = f == key_lane.end() ? (key_lane[kd] = next++ % N_XCD) : f->second;
-                    lane[ln].push_back(make_int2(si, d));
+                    const int ln = f == key_lane.end() ? (key_lane[kd] = next++ % N_XCD) : f->second;
+                    std::vector<int2> run;
+                    for (int q = 0; q < ndw; q++) run.push_back(make_int2(si, doms[r * ndw + q]));
+                    lane[ln].push_back(run);
                 }
+            }
             size_t len = 0;
             for (auto &l : lane) len = std::max(len, l.size());
-            std::vector<int2> items(len * N_XCD, make_int2(-1, -1));
+            std::vector<int2> items(len * N_XCD * ndw, make_int2(-1, -1));
             for (int ln = 0; ln < N_XCD; ln++)
-                for (size_t j = 0; j < lane[ln].size(); j++) items[j * N_XCD + ln] = lane[ln][j];
-            while (!items.empty() && items.back().x < 0) items.pop_back();
+                for (size_t j = 0; j < lane[ln].size(); j++)
+                    for (int q = 0; q < ndw; q++) items[(j * N_XCD + ln) * ndw + q] = lane[ln][j][q];
+            while (!items.empty() && items[items.size() - ndw].x < 0) items.resize(items.size() - ndw);
             G.nitems[col] = (int)items.size();
             HIPCHK(lead, hipMalloc(&G.items[col], sizeof(int2) * std::max<size_t>(1, items.size())));
             HIPCHK(lead, hipMemcpy(G.items[col], items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
@@ -908,6 +917,62 @@ int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double
         sys.push_back({c, c->slots[k].get(), k});
     }
     return solve_systems(sys, x, b, x_is_guess, info, (hipStream_t)stream);
+}
+
+int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
+                      const double *b, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
+                      int domain_out[4], double *ms_out, void *stream)
+{
+    if (!lattice || !boundary || !U || !b || !domain_out) return DDQCD_ERR_ARG;
+    // the compiled shapes that tile this lattice
+    std::vector<std::vector<int>> cand;
+    for (int sh = 0; sh < sap_shape_count(); sh++) {
+        int bd[4];
+        sap_shape_extents(sh, bd);
+        bool ok = true;
+        for (int m = 0; m < 4; m++) {
+            if (lattice[m] < 2 || lattice[m] % bd[m]) ok = false;
+            else if ((lattice[m] / bd[m]) % 2 || lattice[m] / bd[m] < 2) ok = false;
+        }
+        if (ok) cand.push_back({bd[0], bd[1], bd[2], bd[3]});
+    }
+    if (cand.empty()) return DDQCD_ERR_GEOMETRY;
+    if (cand.size() == 1) {   // nothing to choose: no timing
+        for (int m = 0; m < 4; m++) domain_out[m] = cand[0][m];
+        if (ms_out) *ms_out = -1;
+        return DDQCD_OK;
+    }
+    const size_t bytes = (size_t)lattice[0] * lattice[1] * lattice[2] * lattice[3] * 12 * 16;
+    double *x = nullptr;
+    if (hipMalloc(&x, bytes) != hipSuccess) return DDQCD_ERR_NOMEM;
+    double best = 0;
+    int found = 0, last = DDQCD_ERR_GEOMETRY;
+    for (const std::vector<int> &bd : cand) {
+        ddqcd_t c = nullptr;
+        int st = ddqcd_create(lattice, bd.data(), kappa, c_sw, boundary, &c);
+        if (st == DDQCD_OK) st = ddqcd_set_sap(c, n_cycles, n_mr, prec);
+        if (st == DDQCD_OK) st = ddqcd_set_solver(c, restart, tol, max_cycles);
+        if (st == DDQCD_OK) st = ddqcd_load_gauge(c, U, stream);
+        if (st == DDQCD_OK) st = ddqcd_solve(c, x, b, 1, 0, nullptr, stream);   // first call builds the plans
+        double ms = 0;
+        if (st == DDQCD_OK) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = ddqcd_solve(c, x, b, 1, 0, nullptr, stream);
+            ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        ddqcd_destroy(c);
+        if (st == DDQCD_OK && (!found || ms < best)) {
+            best = ms;
+            found = 1;
+            for (int m = 0; m < 4; m++) domain_out[m] = bd[m];
+        } else if (st != DDQCD_OK) {
+            last = st;
+        }
+    }
+    (void)hipFree(x);
+    if (!found) return last;
+    if (ms_out) *ms_out = best;
+    return DDQCD_OK;
 }
 
 }  // extern "C"

@@ -77,6 +77,13 @@ bool sap_shape_supported(const int b[4]);
 bool sap_prec_supported(const int b[4], int prec);
 long sap_face_sites(const int b[4]);
 int sap_shape_id(const int b[4]);
+// Domains one block-solve workgroup takes for (shape, precision): the items
+// of a launch come in runs of this many domains of one system, and a run is
+// never split or padded.
+int sap_domains_per_workgroup(int shape, int prec);
+// The compiled domain shapes: ids 0 .. sap_shape_count() - 1 and their extents.
+int sap_shape_count();
+void sap_shape_extents(int shape, int b[4]);
 // One colour of one half-sweep for a list of (system, domain) items; args and
 // items are device arrays.  All systems share one domain shape (shape id).
 hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,

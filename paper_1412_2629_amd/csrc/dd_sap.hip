@@ -123,6 +123,47 @@ template <int VD, typename T> __device__ __forceinline__ T block_max(T v, T *red
     }
 }
 
+// Reductions over the sites of each domain when NDW domains share a
+// workgroup: wave 0 holds the even sites and wave 1 the odd sites of all NDW
+// domains (NDW * VD / 2 = 64), VD / 2 consecutive lanes per domain.
+template <int VD, int NDW, typename T, int N> __device__ __forceinline__ void slot_sum(T (&v)[N], T *red)
+{
+    if constexpr (NDW == 1) {
+        block_sum<VD, T, N>(v, red);
+    } else {
+        constexpr int VH = VD / 2;
+        static_assert(NDW * VH == 64, "one wave per parity");
+#pragma unroll
+        for (int q = 0; q < N; q++)
+            for (int o = VH / 2; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        const int par = threadIdx.x >> 6, sub = (threadIdx.x & 63) / VH;
+        if ((threadIdx.x % VH) == 0)
+#pragma unroll
+            for (int q = 0; q < N; q++) red[(q * 2 + par) * NDW + sub] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < N; q++) v[q] = red[(q * 2) * NDW + sub] + red[(q * 2 + 1) * NDW + sub];
+        __syncthreads();
+    }
+}
+
+template <int VD, int NDW, typename T> __device__ __forceinline__ T slot_max(T v, T *red)
+{
+    if constexpr (NDW == 1) {
+        return block_max<VD, T>(v, red);
+    } else {
+        constexpr int VH = VD / 2;
+        static_assert(NDW * VH == 64, "one wave per parity");
+        for (int o = VH / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+        const int par = threadIdx.x >> 6, sub = (threadIdx.x & 63) / VH;
+        if ((threadIdx.x % VH) == 0) red[par * NDW + sub] = v;
+        __syncthreads();
+        const T m = fmax(red[sub], red[NDW + sub]);
+        __syncthreads();
+        return m;
+    }
+}
+
 // smallest power of two >= m (m > 0), 1 for m == 0
 template <typename T> __device__ __forceinline__ T pow2_ceil(T m)
 {
@@ -518,18 +559,30 @@ __device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12
 // per link (6: two rows, 9: full).  LINK_LDS stages the domain's links into
 // LDS (else they are read from global memory at each use); CL_REG keeps the
 // site's clover block in registers (else it is read from global memory).
-template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS, bool CL_REG>
+//
+// NDW domains share a workgroup (NDW > 1 for domains of fewer than 64 sites):
+// wave 0 then holds the even sites and wave 1 the odd sites of all of them,
+// so each phase of the even-odd MR step runs one full wave; d is the calling
+// thread's domain.
+template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS,
+          bool CL_REG>
 __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
 {
     constexpr int VD = Sh::VD, VH = Sh::VH;
-    __shared__ v2<G> slink[LINK_LDS ? 4 * NLC * VD : 1];   // [mu][NLC][VD]
-    __shared__ cx<T> she[12][VH];
-    __shared__ cx<T> sho[12][VH];
-    __shared__ T red[VD >= 64 ? 3 * (VD / 64) : 3 * VD];
+    static_assert(NDW == 1 || NDW * VH == 64, "packed domains: one wave per parity");
+    __shared__ v2<G> slink_all[NDW][LINK_LDS ? 4 * NLC * VD : 1];   // [mu][NLC][VD] per domain
+    __shared__ cx<T> she_all[NDW][12][VH];
+    __shared__ cx<T> sho_all[NDW][12][VH];
+    __shared__ T red[NDW > 1 ? 6 * NDW : VD >= 64 ? 3 * (VD / 64) : 3 * VD];
 
-    const int loc = threadIdx.x;
-    const int par = loc >= VH;
-    const int hi = loc - par * VH;
+    const int par = (int)threadIdx.x / (NDW * VH);
+    const int idx = (int)threadIdx.x - par * (NDW * VH);
+    const int sub = idx / VH;   // this thread's domain within the workgroup
+    const int hi = idx - sub * VH;
+    const int loc = par * VH + hi;
+    v2<G> *slink = slink_all[sub];
+    cx<T>(*she)[VH] = she_all[sub];
+    cx<T>(*sho)[VH] = sho_all[sub];
     int l[4];
     Sh::coords(loc, l);
     int D[4];
@@ -642,7 +695,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
                 dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
             }
         }
-        block_sum<VD, T, 3>(dots, red);
+        slot_sum<VD, NDW, T, 3>(dots, red);
         if (par == 0) {
             cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
 #pragma unroll
@@ -685,7 +738,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         for (int k = 0; k < 12; k++) rr[k] = par == 0 ? she[k][hi] : czero<T>();
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = pow2_ceil(block_max<VD, T>(maxabs12(rr), red));
+            sc = pow2_ceil(slot_max<VD, NDW, T>(maxabs12(rr), red));
             if (loc == 0) a.res_scale[d] = (float)sc;
         }
         if (par == 0) {
@@ -698,7 +751,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     if (f.faces_out) {
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = T(8) * pow2_ceil(block_max<VD, T>(maxabs12(A), red));
+            sc = T(8) * pow2_ceil(slot_max<VD, NDW, T>(maxabs12(A), red));
             if (loc == 0) a.face_scale[d] = (float)sc;
         }
         T inv = T(1) / sc;
@@ -870,14 +923,19 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 // domain) and that system's arguments.  Items with system < 0 are padding;
 // systems with active == 0 (already converged) are skipped.
 
-template <class Sh, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS, bool CL_REG>
-__global__ __launch_bounds__(Sh::VD) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
+// With NDW > 1, items come in runs of NDW domains of one system (the plan
+// never splits or pads a run), and workgroup i takes run i.
+template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS,
+          bool CL_REG>
+__global__ __launch_bounds__(Sh::VD * NDW) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
 {
-    const int2 it = items[blockIdx.x];
+    const int2 it = items[(long)blockIdx.x * NDW];
     if (it.x < 0) return;
     const SapArgs a = args[it.x];
     if (!a.active) return;
-    lds_block_solve<Sh, T, SS, PS, G, NLC, SCALED, LINK_LDS, CL_REG>(a, it.y, v);
+    int d = it.y;
+    if constexpr (NDW > 1) d = items[(long)blockIdx.x * NDW + ((int)threadIdx.x & 63) / Sh::VH].y;
+    lds_block_solve<Sh, NDW, T, SS, PS, G, NLC, SCALED, LINK_LDS, CL_REG>(a, d, v);
 }
 
 template <class Sh>
@@ -982,7 +1040,7 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
         if (!__builtin_amdgcn_readfirstlane(ok_s)) continue;
         __atomic_thread_fence(__ATOMIC_ACQUIRE);   // system scope: see the neighbours' results
         const int last = s == q.n_cycles - 1;
-        lds_block_solve<Sh, float, SS, float, G, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
+        lds_block_solve<Sh, 1, float, SS, float, G, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
         __threadfence_system();                     // this block's results reach memory ...
         __syncthreads();
         if (threadIdx.x == 0)                       // ... before its epoch moves on
@@ -1003,26 +1061,43 @@ __global__ void k_epoch_reset(int *epoch, int nd, int *error)
 template <class Sh>
 static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
 {
-    if (prec == P64 && Sh::VD == 16)
-        hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
-                           dim3(Sh::VH), 0, s, args, items, v);
-    else if (prec == P64)
-        hipLaunchKernelGGL((k_sap_f64<Sh>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
-    else if (prec == P32)
-        hipLaunchKernelGGL((k_sap_lds<Sh, float, float, float, float, 6, false, true, true>), dim3(nitems),
-                           dim3(Sh::VD), 0, s, args, items, v);
-    else
-        hipLaunchKernelGGL((k_sap_lds<Sh, float, half_t, float, half_t, 6, true, true, true>), dim3(nitems),
-                           dim3(Sh::VD), 0, s, args, items, v);
+    if (prec == P64) {
+        // FP64: one thread per even/odd site pair on 2^4 domains, else the LDS layout
+        if constexpr (Sh::VD == 16)
+            hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
+                               dim3(Sh::VH), 0, s, args, items, v);
+        else
+            hipLaunchKernelGGL((k_sap_f64<Sh>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
+    } else {
+        constexpr int NDW = Sh::VD < 64 ? 128 / Sh::VD : 1;
+        if (nitems % NDW) return hipErrorInvalidValue;
+        if (prec == P32)
+            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, float, float, float, 6, false, true, true>),
+                               dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
+        else
+            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, true, true, true>),
+                               dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
+    }
     return hipGetLastError();
 }
+
+int sap_domains_per_workgroup(int shape, int prec) { return shape == 0 && prec != P64 ? 8 : 1; }
 
 int sap_shape_id(const int b[4])
 {
     if (b[0] == 2 && b[1] == 2 && b[2] == 2 && b[3] == 2) return 0;
     if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 1;
     if (b[0] == 8 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 2;
+    if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 8) return 3;
     return -1;
+}
+
+int sap_shape_count() { return 4; }
+
+void sap_shape_extents(int shape, int b[4])
+{
+    static const int E[4][4] = {{2, 2, 2, 2}, {4, 4, 4, 4}, {8, 4, 4, 4}, {4, 4, 4, 8}};
+    for (int m = 0; m < 4; m++) b[m] = E[shape][m];
 }
 
 bool sap_shape_supported(const int b[4]) { return sap_shape_id(b) >= 0; }
@@ -1076,6 +1151,7 @@ hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, i
         case 0: return launch_batch<Shape<2, 2, 2, 2>>(args, items, nitems, prec, v, s);
         case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, v, s);
         case 2: return launch_batch<Shape<8, 4, 4, 4>>(args, items, nitems, prec, v, s);
+        case 3: return launch_batch<Shape<4, 4, 4, 8>>(args, items, nitems, prec, v, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -18,7 +18,7 @@ PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP1
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_solver", "ddqcd_load_gauge",
-           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_last_error",
+           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_tune_domain", "ddqcd_last_error",
            "ddqcd_status_string"]
 
 
@@ -58,6 +58,8 @@ def lib():
         L.ddqcd_solve.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
         L.ddqcd_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp), i,
                                         ctypes.POINTER(Info), vp]
+        L.ddqcd_tune_domain.argtypes = [ctypes.POINTER(i), d, d, ctypes.POINTER(d), vp, vp, i, i, i, i, d, i,
+                                        ctypes.POINTER(i), ctypes.POINTER(d), vp]
         L.ddqcd_last_error.argtypes = [vp]
         L.ddqcd_last_error.restype = ctypes.c_char_p
         L.ddqcd_status_string.argtypes = [i]
@@ -184,3 +186,19 @@ def solve_batch(contexts, bs, x0s=None, check=True):
         msg = lib().ddqcd_last_error(contexts[0]._h).decode()
         raise DDQCDError(st, f"solve_batch: {status_string(st)}: {msg}")
     return xs, [i.as_dict() for i in infos], st
+
+
+def tune_domain(lattice, kappa, csw, U, b, prec="f16", n_cycles=16, n_mr=5, restart=16, tol=1e-10, max_cycles=64,
+                boundary=(1.0, 1.0, 1.0, -1.0)):
+    """The fastest compiled domain shape for this lattice and gauge field
+    (ddqcd_tune_domain).  Returns (domain, ms); ms is -1 when only one shape
+    fits and nothing was timed."""
+    dom = (ctypes.c_int * 4)()
+    ms = ctypes.c_double()
+    st = lib().ddqcd_tune_domain((ctypes.c_int * 4)(*[int(v) for v in lattice]), ctypes.c_double(kappa),
+                                 ctypes.c_double(csw), (ctypes.c_double * 4)(*[float(v) for v in boundary]),
+                                 _ptr(U, "U"), _ptr(b, "b"), PREC[prec], n_cycles, n_mr, restart,
+                                 ctypes.c_double(tol), max_cycles, dom, ctypes.byref(ms), _stream())
+    if st != OK:
+        raise DDQCDError(st, f"tune_domain({tuple(lattice)}): {status_string(st)}")
+    return tuple(dom), ms.value

@@ -65,4 +65,5 @@ SMALL = [
     Case("4x8x4x12/2^4", (4, 8, 4, 12), (2, 2, 2, 2), 0.1365, 1.7, 0.6, 111, 4, 3),
     Case("8^4/4^4", (8, 8, 8, 8), (4, 4, 4, 4), 0.13, 1.5, 0.5, 121, 4, 5),
     Case("16x8x8x8/8x4^3", (16, 8, 8, 8), (8, 4, 4, 4), 0.1355, 1.5, 0.5, 131, 4, 5),
+    Case("8x8x8x16/4^3x8", (8, 8, 8, 16), (4, 4, 4, 8), 0.13, 1.5, 0.5, 141, 4, 5),
 ]

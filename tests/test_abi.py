@@ -109,6 +109,25 @@ def test_solve_batch_host_checks():
         assert L.ddqcd_destroy(h2) == ddqcd.OK
 
 
+def test_tune_domain_host_paths():
+    """Shape enumeration happens before any device work: no fitting shape is a
+    geometry error, a single fitting shape is returned without timing."""
+    L = ddqcd.lib()
+    dom = (ctypes.c_int * 4)()
+    ms = ctypes.c_double(0)
+    bc = (ctypes.c_double * 4)(1, 1, 1, -1)
+    dummy, dummy2 = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+
+    def tune(lat):
+        return L.ddqcd_tune_domain((ctypes.c_int * 4)(*lat), 0.13, 1.5, bc, dummy, dummy2, 2, 16, 5, 16, 1e-10, 64,
+                                   dom, ctypes.byref(ms), None)
+    assert L.ddqcd_tune_domain(None, 0.13, 1.5, bc, dummy, dummy2, 2, 16, 5, 16, 1e-10, 64, dom, None,
+                               None) == ddqcd.ERR_ARG
+    assert tune((6, 6, 6, 6)) == ddqcd.ERR_GEOMETRY          # 6 = 2 x 3: odd domain count
+    assert tune((12, 12, 12, 24)) == ddqcd.OK                 # only 2^4 tiles it
+    assert tuple(dom) == (2, 2, 2, 2) and ms.value == -1
+
+
 def test_status_strings():
     assert ddqcd.status_string(ddqcd.ERR_NOT_CONVERGED) == "DDQCD_ERR_NOT_CONVERGED"
     assert ddqcd.status_string(99) == "unknown status"

@@ -149,3 +149,17 @@ def test_graph_schedule_batch():
         assert st_g == st_s == 0
         for xg, xs in zip(xs_g, xs_s):
             assert np.array_equal(host(xg), host(xs))
+
+
+def test_tune_domain_picks_a_converging_shape():
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[2]   # 8^4: 2^4 and 4^4 domains fit
+    f = dev(case.source(95))
+    dom, ms = ddqcd.tune_domain(case.L, case.kappa, case.csw, dev(case.U), f, prec="f16", n_cycles=4, n_mr=5)
+    print(f"tuned domain {dom} ({ms:.2f} ms)")
+    assert dom in ((2, 2, 2, 2), (4, 4, 4, 4)) and ms > 0
+    ctx = ddqcd.Context(case.L, dom, case.kappa, case.csw, BC)
+    ctx.load_gauge(dev(case.U))
+    ctx.set_sap(4, 5, "f16")
+    x, info, st = ctx.solve(f)
+    assert st == ddqcd.OK
