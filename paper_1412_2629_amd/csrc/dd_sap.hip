@@ -564,13 +564,18 @@ __device__ __forceinline__ void clover_reg(const v2<G> cl[36], const cx<T> in[12
 // wave 0 then holds the even sites and wave 1 the odd sites of all of them,
 // so each phase of the even-odd MR step runs one full wave; d is the calling
 // thread's domain.
-template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS,
-          bool CL_REG>
+//
+// LNLC: complex numbers per link kept in LDS (6, as stored, or 9: the third
+// row rebuilt once at staging instead of at every use).
+template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, int LNLC, bool SCALED,
+          bool LINK_LDS, bool CL_REG>
 __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
 {
     constexpr int VD = Sh::VD, VH = Sh::VH;
+    constexpr int HNLC = LINK_LDS ? LNLC : NLC;   // link layout the hops read
     static_assert(NDW == 1 || NDW * VH == 64, "packed domains: one wave per parity");
-    __shared__ v2<G> slink_all[NDW][LINK_LDS ? 4 * NLC * VD : 1];   // [mu][NLC][VD] per domain
+    static_assert(LNLC == NLC || (LNLC == 9 && NLC == 6), "links in LDS: as stored, or two rows made three");
+    __shared__ v2<G> slink_all[NDW][LINK_LDS ? 4 * LNLC * VD : 1];   // [mu][LNLC][VD] per domain
     __shared__ cx<T> she_all[NDW][12][VH];
     __shared__ cx<T> sho_all[NDW][12][VH];
     __shared__ T red[NDW > 1 ? 6 * NDW : VD >= 64 ? 3 * (VD / 64) : 3 * VD];
@@ -600,10 +605,17 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     // ---- stage the links into LDS, the site's clover block into registers
     const v2<G> *links = slink;
     long lbase = 0;
-    if constexpr (LINK_LDS) {
+    if constexpr (LINK_LDS && LNLC == NLC) {
         const long lb = (long)d * 4 * NLC * VD + loc;
 #pragma unroll
         for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = glinks[lb + (long)q * VD];
+    } else if constexpr (LINK_LDS) {
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            const su3<T> U = ld_link<T, G, NLC>(glinks, (long)d * 4 * NLC * VD + (long)mu * NLC * VD + loc, VD);
+#pragma unroll
+            for (int e = 0; e < 9; e++) st<T, G>(slink, (long)(mu * 9 + e) * VD + loc, U.m[e]);
+        }
     } else {
         links = glinks;
         lbase = (long)d * 4 * NLC * VD;
@@ -651,7 +663,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     // the even-site MR residual r lives in its own slot of she for the whole
     // solve (fewer live registers); x stays in the registers of A
     if (par == 0) {
-        dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, P);
+        dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, P);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             she[k][hi] = A[k] + scal(T(0.5), P[k]);
@@ -672,7 +684,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         __syncthreads();
         if (par == 1) {
             cx<T> t[12];
-            dom_hops<Sh, T, G, NLC>(she, l, lbase, loc, links, t);
+            dom_hops<Sh, T, G, HNLC>(she, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) t[k] = scal(T(-0.5), t[k]);   // D_oe r
             clover(t, P);                                // C_o^-1 D_oe r
@@ -683,7 +695,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         T dots[3] = {0, 0, 0};
         if (par == 0) {
             cx<T> t[12], rr[12];
-            dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, t);
+            dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) rr[k] = she[k][hi];
             clover(rr, P);                               // C_e r
@@ -715,7 +727,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     __syncthreads();
     if (par == 1) {
         cx<T> t[12];
-        dom_hops<Sh, T, G, NLC>(sho, l, lbase, loc, links, t);
+        dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
         clover(t, A);
@@ -925,8 +937,8 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 
 // With NDW > 1, items come in runs of NDW domains of one system (the plan
 // never splits or pads a run), and workgroup i takes run i.
-template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, bool SCALED, bool LINK_LDS,
-          bool CL_REG>
+template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, int LNLC, bool SCALED,
+          bool LINK_LDS, bool CL_REG>
 __global__ __launch_bounds__(Sh::VD * NDW) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
 {
     const int2 it = items[(long)blockIdx.x * NDW];
@@ -935,7 +947,7 @@ __global__ __launch_bounds__(Sh::VD * NDW) void k_sap_lds(const SapArgs *args, c
     if (!a.active) return;
     int d = it.y;
     if constexpr (NDW > 1) d = items[(long)blockIdx.x * NDW + ((int)threadIdx.x & 63) / Sh::VH].y;
-    lds_block_solve<Sh, NDW, T, SS, PS, G, NLC, SCALED, LINK_LDS, CL_REG>(a, d, v);
+    lds_block_solve<Sh, NDW, T, SS, PS, G, NLC, LNLC, SCALED, LINK_LDS, CL_REG>(a, d, v);
 }
 
 template <class Sh>
@@ -1040,7 +1052,7 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
         if (!__builtin_amdgcn_readfirstlane(ok_s)) continue;
         __atomic_thread_fence(__ATOMIC_ACQUIRE);   // system scope: see the neighbours' results
         const int last = s == q.n_cycles - 1;
-        lds_block_solve<Sh, 1, float, SS, float, G, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
+        lds_block_solve<Sh, 1, float, SS, float, G, 6, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
         __threadfence_system();                     // this block's results reach memory ...
         __syncthreads();
         if (threadIdx.x == 0)                       // ... before its epoch moves on
@@ -1072,10 +1084,10 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
         constexpr int NDW = Sh::VD < 64 ? 128 / Sh::VD : 1;
         if (nitems % NDW) return hipErrorInvalidValue;
         if (prec == P32)
-            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, float, float, float, 6, false, true, true>),
+            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, float, float, float, 6, 6, false, true, true>),
                                dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
         else
-            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, true, true, true>),
+            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, 9, true, true, true>),
                                dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
     }
     return hipGetLastError();
