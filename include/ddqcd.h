@@ -81,7 +81,8 @@ typedef struct {
 /* Creates a context for one lattice (host metadata only; no device memory).
  * lattice[4]: Lx, Ly, Lz, Lt.  domain[4]: Schwarz domain extents; each must be
  * even, divide the lattice extent, and leave an even number >= 2 of domains
- * per direction (black/white colouring of Sec. IV-B2).  kappa > 0 gives
+ * per direction (black/white colouring of Sec. IV-B2), and be one of the
+ * compiled block-solve shapes 2x2x2x2, 4x4x4x4, 8x4x4x4, 4x4x4x8, 6x6x2x4.  kappa > 0 gives
  * 4 + m = 1/(2 kappa) (Sec. II-B).  boundary[mu] in {+1, -1}.
  * Defaults: SAP 16 cycles, 5 MR steps, FP32 (Sec. IV-C); FGCR restart 16,
  * tol 1e-10, max 64 cycles.  Returns DDQCD_ERR_GEOMETRY / DDQCD_ERR_ARG on
@@ -162,8 +163,9 @@ int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double
  * parallelism) against the strength of the preconditioner (larger blocks,
  * fewer outer iterations; Sec. II-D, IV-C), and the best trade depends on the
  * lattice and the gauge field, so it is measured: for every compiled
- * block-solve shape that tiles the lattice with an even number (>= 2) of
- * domains in each direction, a context is created, U loaded (device pointer,
+ * block-solve shape (2x2x2x2, 4x4x4x4, 8x4x4x4, 4x4x4x8, 6x6x2x4; 6x6x2x4 has
+ * no FP64 kernel) that tiles the lattice with an even number (>= 2) of
+ * domains in each direction and has a kernel for prec, a context is created, U loaded (device pointer,
  * canonical layout) and b solved (device pointer, canonical layout, one
  * right-hand side) twice with the given settings; the second solve is timed.
  * The fastest shape that converged is written to domain_out and its solve time

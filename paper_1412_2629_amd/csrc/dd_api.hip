@@ -375,31 +375,58 @@ int apply_A64(ddqcd_t c, const double2 *in, double2 *out, hipStream_t s)
     return DDQCD_OK;
 }
 
-struct Timer {
-    hipEvent_t a = nullptr, b = nullptr;
+// Phase timings of a solve: each phase is bracketed by two events on the
+// launch stream; the elapsed times are read once at the end (no extra
+// synchronisation between phases).
+struct Clock {
+    struct Span {
+        hipEvent_t a, b;
+        double *acc;
+    };
+    std::vector<Span> spans;
     hipStream_t s;
-    double *acc;
-    Timer(hipStream_t s_, double *acc_) : s(s_), acc(acc_)
+    explicit Clock(hipStream_t s_) : s(s_) {}
+    void collect()
     {
-        if (acc) {
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
-            (void)hipEventRecord(a, s);
+        if (spans.empty()) return;
+        (void)hipEventSynchronize(spans.back().b);
+        for (Span &p : spans) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) *p.acc += ms;
         }
+        release();
     }
-    void stop()
+    void release()
     {
-        if (!acc) return;
-        (void)hipEventRecord(b, s);
-        (void)hipEventSynchronize(b);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        *acc += ms;
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        acc = nullptr;
+        for (Span &p : spans) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        spans.clear();
     }
-    ~Timer() { stop(); }
+    ~Clock() { release(); }
+};
+
+struct Timer {
+    Clock &clk;
+    Clock::Span sp{nullptr, nullptr, nullptr};
+    Timer(Clock &c, double *acc) : clk(c)
+    {
+        if (hipEventCreate(&sp.a) != hipSuccess) return;
+        if (hipEventCreate(&sp.b) != hipSuccess) {
+            (void)hipEventDestroy(sp.a);
+            sp.a = nullptr;
+            return;
+        }
+        sp.acc = acc;
+        (void)hipEventRecord(sp.a, clk.s);
+    }
+    ~Timer()
+    {
+        if (!sp.acc) return;
+        (void)hipEventRecord(sp.b, clk.s);
+        clk.spans.push_back(sp);
+    }
 };
 
 using C = std::complex<double>;
@@ -445,6 +472,7 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
     const int max_cycles = lead->max_cycles;
     const double tol = lead->tol;
     double tsap = 0, tA = 0, tgs = 0, tother = 0;
+    Clock clk(s);
     std::vector<FgcrState> st(ns);
     int e;
     for (int i = 0; i < ns; i++) {
@@ -476,12 +504,12 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
         } else live.push_back(i);
     }
     {
-        Timer t(s, &tA);
+        Timer t(clk, &tA);
         for (int i : live)
             if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
     }
     {
-        Timer t(s, &tother);
+        Timer t(clk, &tother);
         for (int i : live) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
         if ((e = fetch_all(sys, st, live, 1, s))) return e;
     }
@@ -509,7 +537,7 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             if (act.empty()) break;
             // z_k = M r
             {
-                Timer t(s, &tsap);
+                Timer t(clk, &tsap);
                 std::vector<const double2 *> eta(ns);
                 std::vector<double2 *> out(ns);
                 std::vector<int> on(ns, 0);
@@ -522,12 +550,12 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             }
             // w_k = A z_k
             {
-                Timer t(s, &tA);
+                Timer t(clk, &tA);
                 for (int i : act)
                     if ((e = apply_A64(sys[i].c, Zk(i, k), Wk(i, k), s))) return e;
             }
             {
-                Timer t(s, &tgs);
+                Timer t(clk, &tgs);
                 // classical Gram-Schmidt against the earlier w-hat, repeated
                 // once for a system whose new vector lost more than half its norm
                 std::vector<double> before(ns, 0), wn2(ns, 0);
@@ -589,7 +617,7 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
         }
         // x += sum_k alpha_k z_k, then the true residual r = b - A x
         {
-            Timer t(s, &tother);
+            Timer t(clk, &tother);
             for (int i : cur) {
                 FgcrState &f = st[i];
                 for (int k = f.kend - 1; k >= 0; k--) {
@@ -604,12 +632,12 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             }
         }
         {
-            Timer t(s, &tA);
+            Timer t(clk, &tA);
             for (int i : cur)
                 if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
         }
         {
-            Timer t(s, &tother);
+            Timer t(clk, &tother);
             for (int i : cur) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
             if ((e = fetch_all(sys, st, cur, 1, s))) return e;
         }
@@ -624,6 +652,7 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             }
         }
     }
+    clk.collect();
     int status = DDQCD_OK;
     for (int i = 0; i < ns; i++) {
         ddqcd_info &inf = info[i];
@@ -929,7 +958,7 @@ int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const dou
     for (int sh = 0; sh < sap_shape_count(); sh++) {
         int bd[4];
         sap_shape_extents(sh, bd);
-        bool ok = true;
+        bool ok = sap_prec_supported(bd, prec);
         for (int m = 0; m < 4; m++) {
             if (lattice[m] < 2 || lattice[m] % bd[m]) ok = false;
             else if ((lattice[m] / bd[m]) % 2 || lattice[m] / bd[m] < 2) ok = false;

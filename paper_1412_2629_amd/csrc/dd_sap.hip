@@ -27,6 +27,9 @@ namespace dd {
 template <int BX, int BY, int BZ, int BT> struct Shape {
     static constexpr int VD = BX * BY * BZ * BT;
     static constexpr int VH = VD / 2;
+    // threads of a one-domain block-solve workgroup: whole waves (idle padding
+    // threads beyond VD) for domains of 64 sites or more
+    static constexpr int NT = VD >= 64 ? (VD + 63) / 64 * 64 : VD;
     static constexpr int B[4] = {BX, BY, BZ, BT};
     static constexpr int FS[4] = {VD / BX, VD / BY, VD / BZ, VD / BT};
     static constexpr int FTOT = 2 * (VD / BX + VD / BY + VD / BZ + VD / BT);
@@ -572,19 +575,24 @@ template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, i
 __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, const Visit f)
 {
     constexpr int VD = Sh::VD, VH = Sh::VH;
+    constexpr int NT = NDW > 1 ? NDW * VD : Sh::NT;   // threads of the workgroup
+    constexpr int RV = NDW > 1 ? VD : NT;             // reduction width argument
     constexpr int HNLC = LINK_LDS ? LNLC : NLC;   // link layout the hops read
     static_assert(NDW == 1 || NDW * VH == 64, "packed domains: one wave per parity");
     static_assert(LNLC == NLC || (LNLC == 9 && NLC == 6), "links in LDS: as stored, or two rows made three");
     __shared__ v2<G> slink_all[NDW][LINK_LDS ? 4 * LNLC * VD : 1];   // [mu][LNLC][VD] per domain
     __shared__ cx<T> she_all[NDW][12][VH];
     __shared__ cx<T> sho_all[NDW][12][VH];
-    __shared__ T red[NDW > 1 ? 6 * NDW : VD >= 64 ? 3 * (VD / 64) : 3 * VD];
+    __shared__ T red[NDW > 1 ? 6 * NDW : NT >= 64 ? 3 * (NT / 64) : 3 * NT];
 
     const int par = (int)threadIdx.x / (NDW * VH);
     const int idx = (int)threadIdx.x - par * (NDW * VH);
     const int sub = idx / VH;   // this thread's domain within the workgroup
     const int hi = idx - sub * VH;
     const int loc = par * VH + hi;
+    // padding threads (threadIdx >= VD, only when VD is not a multiple of 64)
+    // take part in barriers and reductions with zeros and touch no memory
+    const bool live = NDW > 1 || NT == VD || (int)threadIdx.x < VD;
     v2<G> *slink = slink_all[sub];
     cx<T>(*she)[VH] = she_all[sub];
     cx<T>(*sho)[VH] = sho_all[sub];
@@ -605,7 +613,8 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     // ---- stage the links into LDS, the site's clover block into registers
     const v2<G> *links = slink;
     long lbase = 0;
-    if constexpr (LINK_LDS && LNLC == NLC) {
+    if (!live) {
+    } else if constexpr (LINK_LDS && LNLC == NLC) {
         const long lb = (long)d * 4 * NLC * VD + loc;
 #pragma unroll
         for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = glinks[lb + (long)q * VD];
@@ -624,7 +633,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     v2<G> cl[CL_REG ? 36 : 1];
     if constexpr (CL_REG) {
 #pragma unroll
-        for (int q = 0; q < 36; q++) cl[q] = cs[cbase + (long)q * VD];
+        for (int q = 0; q < 36; q++) cl[q] = live ? cs[cbase + (long)q * VD] : v2<G>{};
     }
     // this site's clover block (C_e on even sites, C_o^-1 on odd sites) times in
     auto clover = [&](const cx<T> in[12], cx<T> out[12]) {
@@ -634,7 +643,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 
     // A: even sites x (MR solution), odd sites rho_o then delta_o
     cx<T> A[12], P[12];
-    if (f.first) {
+    if (!live) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) A[k] = czero<T>();
+    } else if (f.first) {
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
     } else if (par == 0) {
@@ -646,7 +658,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = czero<T>();
     }
-    if (f.faces_in) {
+    if (f.faces_in && live) {
         gather_face<Sh, 0, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
         gather_face<Sh, 1, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
         gather_face<Sh, 2, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
@@ -707,7 +719,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
                 dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
             }
         }
-        slot_sum<VD, NDW, T, 3>(dots, red);
+        slot_sum<RV, NDW, T, 3>(dots, red);
         if (par == 0) {
             cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
 #pragma unroll
@@ -734,7 +746,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     }
 
     // ---- epilogue
-    {
+    if (live) {
         const v2<PS> *psi_in = (const v2<PS> *)a.psi;
         v2<PS> *psi_out = (v2<PS> *)a.psi;
 #pragma unroll
@@ -750,7 +762,7 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         for (int k = 0; k < 12; k++) rr[k] = par == 0 ? she[k][hi] : czero<T>();
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = pow2_ceil(slot_max<VD, NDW, T>(maxabs12(rr), red));
+            sc = pow2_ceil(slot_max<RV, NDW, T>(maxabs12(rr), red));
             if (loc == 0) a.res_scale[d] = (float)sc;
         }
         if (par == 0) {
@@ -763,14 +775,16 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     if (f.faces_out) {
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = T(8) * pow2_ceil(slot_max<VD, NDW, T>(maxabs12(A), red));
+            sc = T(8) * pow2_ceil(slot_max<RV, NDW, T>(maxabs12(A), red));
             if (loc == 0) a.face_scale[d] = (float)sc;
         }
         T inv = T(1) / sc;
-        write_face<Sh, 0, T, SS, G, NLC>(a, d, l, loc, A, inv);
-        write_face<Sh, 1, T, SS, G, NLC>(a, d, l, loc, A, inv);
-        write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, A, inv);
-        write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, A, inv);
+        if (live) {
+            write_face<Sh, 0, T, SS, G, NLC>(a, d, l, loc, A, inv);
+            write_face<Sh, 1, T, SS, G, NLC>(a, d, l, loc, A, inv);
+            write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, A, inv);
+            write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, A, inv);
+        }
     }
 }
 
@@ -939,7 +953,8 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 // never splits or pads a run), and workgroup i takes run i.
 template <class Sh, int NDW, typename T, typename SS, typename PS, typename G, int NLC, int LNLC, bool SCALED,
           bool LINK_LDS, bool CL_REG>
-__global__ __launch_bounds__(Sh::VD * NDW) void k_sap_lds(const SapArgs *args, const int2 *items, Visit v)
+__global__ __launch_bounds__(NDW > 1 ? Sh::VD * NDW : Sh::NT) void k_sap_lds(const SapArgs *args, const int2 *items,
+                                                                             Visit v)
 {
     const int2 it = items[(long)blockIdx.x * NDW];
     if (it.x < 0) return;
@@ -1074,21 +1089,25 @@ template <class Sh>
 static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
 {
     if (prec == P64) {
-        // FP64: one thread per even/odd site pair on 2^4 domains, else the LDS layout
+        // FP64: one thread per even/odd site pair on 2^4 domains, else the LDS
+        // layout (whole waves only: no FP64 kernel for padded workgroups)
         if constexpr (Sh::VD == 16)
             hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
                                dim3(Sh::VH), 0, s, args, items, v);
-        else
+        else if constexpr (Sh::VD % 64 == 0)
             hipLaunchKernelGGL((k_sap_f64<Sh>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
+        else
+            return hipErrorInvalidValue;
     } else {
         constexpr int NDW = Sh::VD < 64 ? 128 / Sh::VD : 1;
+        constexpr int NT = NDW > 1 ? Sh::VD * NDW : Sh::NT;
         if (nitems % NDW) return hipErrorInvalidValue;
         if (prec == P32)
             hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, float, float, float, 6, 6, false, true, true>),
-                               dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
+                               dim3(nitems / NDW), dim3(NT), 0, s, args, items, v);
         else
             hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, 9, true, true, true>),
-                               dim3(nitems / NDW), dim3(Sh::VD * NDW), 0, s, args, items, v);
+                               dim3(nitems / NDW), dim3(NT), 0, s, args, items, v);
     }
     return hipGetLastError();
 }
@@ -1101,20 +1120,28 @@ int sap_shape_id(const int b[4])
     if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 1;
     if (b[0] == 8 && b[1] == 4 && b[2] == 4 && b[3] == 4) return 2;
     if (b[0] == 4 && b[1] == 4 && b[2] == 4 && b[3] == 8) return 3;
+    if (b[0] == 6 && b[1] == 6 && b[2] == 2 && b[3] == 4) return 4;
     return -1;
 }
 
-int sap_shape_count() { return 4; }
+int sap_shape_count() { return 5; }
 
 void sap_shape_extents(int shape, int b[4])
 {
-    static const int E[4][4] = {{2, 2, 2, 2}, {4, 4, 4, 4}, {8, 4, 4, 4}, {4, 4, 4, 8}};
+    static const int E[5][4] = {{2, 2, 2, 2}, {4, 4, 4, 4}, {8, 4, 4, 4}, {4, 4, 4, 8}, {6, 6, 2, 4}};
     for (int m = 0; m < 4; m++) b[m] = E[shape][m];
 }
 
 bool sap_shape_supported(const int b[4]) { return sap_shape_id(b) >= 0; }
 
-bool sap_prec_supported(const int b[4], int prec) { return sap_shape_id(b) >= 0 && prec >= P64 && prec <= P16; }
+// FP64 block solves need 16 sites or whole waves (no padded FP64 workgroups)
+bool sap_prec_supported(const int b[4], int prec)
+{
+    const int id = sap_shape_id(b);
+    if (id < 0 || prec < P64 || prec > P16) return false;
+    const int vd = b[0] * b[1] * b[2] * b[3];
+    return prec != P64 || vd == 16 || vd % 64 == 0;
+}
 
 long sap_face_sites(const int b[4])
 {
@@ -1164,6 +1191,7 @@ hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, i
         case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, v, s);
         case 2: return launch_batch<Shape<8, 4, 4, 4>>(args, items, nitems, prec, v, s);
         case 3: return launch_batch<Shape<4, 4, 4, 8>>(args, items, nitems, prec, v, s);
+        case 4: return launch_batch<Shape<6, 6, 2, 4>>(args, items, nitems, prec, v, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -66,4 +66,14 @@ SMALL = [
     Case("8^4/4^4", (8, 8, 8, 8), (4, 4, 4, 4), 0.13, 1.5, 0.5, 121, 4, 5),
     Case("16x8x8x8/8x4^3", (16, 8, 8, 8), (8, 4, 4, 4), 0.1355, 1.5, 0.5, 131, 4, 5),
     Case("8x8x8x16/4^3x8", (8, 8, 8, 16), (4, 4, 4, 8), 0.13, 1.5, 0.5, 141, 4, 5),
+    Case("12x12x4x8/6x6x2x4", (12, 12, 4, 8), (6, 6, 2, 4), 0.13, 1.5, 0.5, 151, 4, 5),
 ]
+
+# Block solves on 288-site domains run in 320-thread workgroups with idle
+# padding threads; the FP64 block-solve kernels are built for whole waves (or
+# 16-site domains) only, and the library rejects FP64 for this shape.
+NO_FP64_SAP = "no FP64 block-solve kernel for 6x6x2x4 domains (padded workgroups)"
+
+
+def fp64_sap(case):
+    return case.b != (6, 6, 2, 4)

@@ -124,7 +124,7 @@ def test_tune_domain_host_paths():
     assert L.ddqcd_tune_domain(None, 0.13, 1.5, bc, dummy, dummy2, 2, 16, 5, 16, 1e-10, 64, dom, None,
                                None) == ddqcd.ERR_ARG
     assert tune((6, 6, 6, 6)) == ddqcd.ERR_GEOMETRY          # 6 = 2 x 3: odd domain count
-    assert tune((12, 12, 12, 24)) == ddqcd.OK                 # only 2^4 tiles it
+    assert tune((4, 4, 4, 4)) == ddqcd.OK                     # only 2^4 tiles it
     assert tuple(dom) == (2, 2, 2, 2) and ms.value == -1
 
 

@@ -10,7 +10,7 @@ Tolerances (normwise relative errors):
 import numpy as np
 import pytest
 
-from tests.gpu_cases import BC, SMALL, Case, dev, host, rel
+from tests.gpu_cases import BC, NO_FP64_SAP, SMALL, Case, dev, fp64_sap, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,8 @@ def test_apply_D_batched_rhs(oracle):
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
 def test_sap_fp64(case, oracle):
+    if not fp64_sap(case):
+        pytest.skip(NO_FP64_SAP)
     eta = case.source(5)
     want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
     ctx = case.context("f64")
@@ -119,6 +121,8 @@ def test_sap_homogeneous(case):
 @pytest.mark.parametrize("case", SMALL, ids=repr)
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_solve(case, prec, oracle):
+    if prec == "f64" and not fp64_sap(case):
+        pytest.skip(NO_FP64_SAP)
     f = case.source(3)
     x_or, st, steps, rr = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
                                       n_mr=case.n_mr, restart=16, tol=1e-12)
@@ -200,3 +204,11 @@ def test_two_contexts_independent(oracle):
     gb = host(cb.apply_D(dev(pb)))
     assert rel(ga, oracle.apply_A(a.L, BC, a.U, a.C, pa)) <= 1e-13
     assert rel(gb, oracle.apply_A(b.L, BC, b.U, b.C, pb)) <= 1e-13
+
+
+def test_fp64_sap_rejected_on_padded_domains():
+    from paper_1412_2629_amd import ddqcd
+    ctx = SMALL[5].context()
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ctx.set_sap(4, 5, "f64")
+    assert e.value.status == ddqcd.ERR_GEOMETRY
