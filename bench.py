@@ -32,7 +32,7 @@ CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 # they were taken on, identified by a hash; after any change to those sources
 # the figure is reported as null until it is measured again.
 KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
-MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.36e6, "sources": "15aa65bcb5a887d7"}}
+MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.36e6, "sources": "a166705087465ae1"}}
 
 
 def log(*a):

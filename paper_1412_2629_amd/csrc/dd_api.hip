@@ -89,6 +89,10 @@ struct ddqcd_ctx {
     void *Cs32 = nullptr, *Cs16 = nullptr;
     void *t_lo_in = nullptr, *t_lo_out = nullptr;   // FP32/FP16 operands of apply_D
     hipStream_t capture = nullptr;   // private stream on which launch graphs are captured
+    // reduction results of the systems of a solve led by this context, side by
+    // side (32 pairs each) on the device and in pinned host memory
+    double2 *res_dev = nullptr, *res_host = nullptr;
+    int res_cap = 0;
     std::vector<std::unique_ptr<Slot>> slots;
     std::map<std::string, std::unique_ptr<Plan>> plans;   // batch plans led by this context
     std::vector<void *> owned;
@@ -444,13 +448,51 @@ struct FgcrState {
     double2 h[32];          // results of the last reduction
 };
 
-// read back result[0..m-1] of every listed system with one wait
+// During a solve every system's reduction results live side by side in the
+// lead context's result area (system i at pairs [32 i, 32 i + 32)), so one
+// copy into pinned memory and one wait read all of them back.
+struct ResultArea {
+    const std::vector<Sys> &sys;
+    std::vector<double2 *> saved;
+    ddqcd_t lead;
+    explicit ResultArea(const std::vector<Sys> &s) : sys(s), lead(s[0].c) {}
+    int bind()
+    {
+        const int ns = (int)sys.size();
+        if (lead->res_cap < ns) {
+            int e;
+            if ((e = alloc(lead, &lead->res_dev, sizeof(double2) * 32 * ns))) return e;
+            if (lead->res_host) (void)hipHostFree(lead->res_host);
+            lead->res_host = nullptr;
+            lead->res_cap = 0;
+            HIPCHK(lead, hipHostMalloc((void **)&lead->res_host, sizeof(double2) * 32 * ns, hipHostMallocDefault));
+            lead->res_cap = ns;
+        }
+        for (int i = 0; i < ns; i++) {
+            saved.push_back(sys[i].sl->blas.result);
+            sys[i].sl->blas.result = lead->res_dev + 32L * i;
+        }
+        return DDQCD_OK;
+    }
+    ~ResultArea()
+    {
+        for (size_t i = 0; i < saved.size(); i++) sys[i].sl->blas.result = saved[i];
+    }
+};
+
+// read back result[0..m-1] of every listed system with one copy and one wait
 int fetch_all(const std::vector<Sys> &sys, std::vector<FgcrState> &st, const std::vector<int> &which, int m,
               hipStream_t s)
 {
-    for (int i : which)
-        HIPCHK(sys[i].c, hipMemcpyAsync(st[i].h, sys[i].sl->blas.result, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(sys[0].c, hipStreamSynchronize(s));
+    if (which.empty()) return DDQCD_OK;
+    ddqcd_t lead = sys[0].c;
+    const int lo = *std::min_element(which.begin(), which.end());
+    const int hi = *std::max_element(which.begin(), which.end());
+    const size_t off = 32L * lo, len = 32L * (hi - lo) + m;
+    HIPCHK(lead, hipMemcpyAsync(lead->res_host + off, lead->res_dev + off, sizeof(double2) * len,
+                                hipMemcpyDeviceToHost, s));
+    HIPCHK(lead, hipStreamSynchronize(s));
+    for (int i : which) std::copy(lead->res_host + 32L * i, lead->res_host + 32L * i + m, st[i].h);
     return DDQCD_OK;
 }
 
@@ -475,6 +517,8 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
     Clock clk(s);
     std::vector<FgcrState> st(ns);
     int e;
+    ResultArea area(sys);
+    if ((e = area.bind())) return e;
     for (int i = 0; i < ns; i++) {
         st[i].a.assign((size_t)m * m, 0);
         st[i].cc.assign(m, 0);
@@ -769,6 +813,7 @@ int ddqcd_destroy(ddqcd_t c)
     if (!c) return DDQCD_OK;
     c->plans.clear();
     if (c->capture) (void)hipStreamDestroy(c->capture);
+    if (c->res_host) (void)hipHostFree(c->res_host);
     for (void *p : c->owned) (void)hipFree(p);
     delete c;
     return DDQCD_OK;

@@ -438,13 +438,21 @@ template <int N> __device__ __forceinline__ void block_reduce_store(double (&v)[
     }
 }
 
+// blocks of a BLAS launch over n complex elements: about four elements per
+// thread, at most BLAS_NBLK (the size of the partial-sum buffer)
+static int blas_blocks(long n)
+{
+    const long b = (n + 4L * BS - 1) / (4L * BS);
+    return (int)(b < 1 ? 1 : b > BLAS_NBLK ? BLAS_NBLK : b);
+}
+
 // stage 2: result[j] = sum over blocks of partial[b][j], j < m pairs
-__global__ void k_finish(const double2 *partial, int m, double2 *result)
+__global__ void k_finish(const double2 *partial, int nblk, int m, double2 *result)
 {
     __shared__ double2 red[BS];
     for (int j = 0; j < m; j++) {
         double2 s = make_double2(0, 0);
-        for (int b = threadIdx.x; b < BLAS_NBLK; b += BS) {
+        for (int b = threadIdx.x; b < nblk; b += BS) {
             double2 v = partial[(long)b * 32 + j];
             s.x += v.x;
             s.y += v.y;
@@ -468,7 +476,7 @@ template <int K> __global__ __launch_bounds__(BS) void k_multidot(const double2 
     double acc[2 * K];
 #pragma unroll
     for (int q = 0; q < 2 * K; q++) acc[q] = 0;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 b = v[i];
 #pragma unroll
         for (int j = 0; j < K; j++) {
@@ -482,7 +490,7 @@ template <int K> __global__ __launch_bounds__(BS) void k_multidot(const double2 
 
 template <int K> static void launch_multidot(const double2 *W, long ldw, const double2 *v, long n, double2 *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_multidot<K>, BLAS_NBLK, BS, 0, s, W, ldw, v, n, partial);
+    hipLaunchKernelGGL(k_multidot<K>, blas_blocks(n), BS, 0, s, W, ldw, v, n, partial);
 }
 
 hipError_t Blas::init()
@@ -509,7 +517,7 @@ hipError_t multidot(Blas &B, const double2 *W, long ldw, int k, const double2 *v
 #undef MD
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, k, B.result);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), k, B.result);
     return hipGetLastError();
 }
 
@@ -521,7 +529,7 @@ __global__ __launch_bounds__(BS) void k_cgs_update(double2 *w, const double2 *W,
 #pragma unroll
     for (int j = 0; j < K; j++) c[j] = coef[j];
     double acc[4] = {0, 0, 0, 0};
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 x = w[i];
 #pragma unroll
         for (int j = 0; j < K; j++) {
@@ -541,19 +549,19 @@ __global__ __launch_bounds__(BS) void k_cgs_update(double2 *w, const double2 *W,
 hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, const double2 *r, long n, hipStream_t s)
 {
     switch (k) {
-#define CU(K) case K: hipLaunchKernelGGL(k_cgs_update<K>, BLAS_NBLK, BS, 0, s, w, W, ldw, B.coef, r, n, B.partial); break;
+#define CU(K) case K: hipLaunchKernelGGL(k_cgs_update<K>, blas_blocks(n), BS, 0, s, w, W, ldw, B.coef, r, n, B.partial); break;
         CU(0) CU(1) CU(2) CU(3) CU(4) CU(5) CU(6) CU(7) CU(8) CU(9) CU(10) CU(11) CU(12) CU(13) CU(14) CU(15) CU(16)
 #undef CU
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 2, B.result);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 2, B.result);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(BS) void k_normalize_update(double2 *w, double inv_b, double2 *r, double2 c, long n, double2 *partial)
 {
     double acc[2] = {0, 0};
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 x = w[i];
         x.x *= inv_b;
         x.y *= inv_b;
@@ -569,8 +577,8 @@ __global__ __launch_bounds__(BS) void k_normalize_update(double2 *w, double inv_
 
 hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_normalize_update, BLAS_NBLK, BS, 0, s, w, inv_b, r, c, n, B.partial);
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    hipLaunchKernelGGL(k_normalize_update, blas_blocks(n), BS, 0, s, w, inv_b, r, c, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
     return hipGetLastError();
 }
 
@@ -579,7 +587,7 @@ template <int K> __global__ __launch_bounds__(BS) void k_axpy_multi(double2 *x, 
     double2 c[K];
 #pragma unroll
     for (int j = 0; j < K; j++) c[j] = coef[j];
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 y = x[i];
 #pragma unroll
         for (int j = 0; j < K; j++) {
@@ -594,7 +602,7 @@ template <int K> __global__ __launch_bounds__(BS) void k_axpy_multi(double2 *x, 
 hipError_t axpy_multi(Blas &B, double2 *x, const double2 *Z, long ldz, int k, long n, hipStream_t s)
 {
     switch (k) {
-#define AX(K) case K: hipLaunchKernelGGL(k_axpy_multi<K>, BLAS_NBLK, BS, 0, s, x, Z, ldz, B.coef, n); break;
+#define AX(K) case K: hipLaunchKernelGGL(k_axpy_multi<K>, blas_blocks(n), BS, 0, s, x, Z, ldz, B.coef, n); break;
         AX(1) AX(2) AX(3) AX(4) AX(5) AX(6) AX(7) AX(8) AX(9) AX(10) AX(11) AX(12) AX(13) AX(14) AX(15) AX(16)
 #undef AX
         default: return hipErrorInvalidValue;
@@ -605,7 +613,7 @@ hipError_t axpy_multi(Blas &B, double2 *x, const double2 *Z, long ldz, int k, lo
 __global__ __launch_bounds__(BS) void k_residual(const double2 *b, double2 *r, long n, double2 *partial)
 {
     double acc[2] = {0, 0};
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 y = b[i], a = r[i];
         y.x -= a.x;
         y.y -= a.y;
@@ -617,15 +625,15 @@ __global__ __launch_bounds__(BS) void k_residual(const double2 *b, double2 *r, l
 
 hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual, BLAS_NBLK, BS, 0, s, b, r, n, B.partial);
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    hipLaunchKernelGGL(k_residual, blas_blocks(n), BS, 0, s, b, r, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
     return hipGetLastError();
 }
 
 __global__ __launch_bounds__(BS) void k_norm2(const double2 *v, long n, double2 *partial)
 {
     double acc[2] = {0, 0};
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)BLAS_NBLK * BS) {
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
         double2 y = v[i];
         acc[0] += y.x * y.x + y.y * y.y;
     }
@@ -634,8 +642,8 @@ __global__ __launch_bounds__(BS) void k_norm2(const double2 *v, long n, double2 
 
 hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_norm2, BLAS_NBLK, BS, 0, s, v, n, B.partial);
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, 1, B.result);
+    hipLaunchKernelGGL(k_norm2, blas_blocks(n), BS, 0, s, v, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
     return hipGetLastError();
 }
 

@@ -702,20 +702,24 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
             clover(t, P);                                // C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) sho[k][hi] = P[k];
+        } else if (par == 0) {
+            // meanwhile the even sites form C_e r, which needs only r
+            cx<T> rr[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) rr[k] = she[k][hi];
+            clover(rr, P);
         }
         __syncthreads();
         T dots[3] = {0, 0, 0};
         if (par == 0) {
-            cx<T> t[12], rr[12];
+            cx<T> t[12];
             dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
-            for (int k = 0; k < 12; k++) rr[k] = she[k][hi];
-            clover(rr, P);                               // C_e r
-#pragma unroll
             for (int k = 0; k < 12; k++) {
+                const cx<T> rk = she[k][hi];
                 P[k] = P[k] + scal(T(0.5), t[k]);
-                dots[0] += P[k].r * rr[k].r + P[k].i * rr[k].i;
-                dots[1] += P[k].r * rr[k].i - P[k].i * rr[k].r;
+                dots[0] += P[k].r * rk.r + P[k].i * rk.i;
+                dots[1] += P[k].r * rk.i - P[k].i * rk.r;
                 dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
             }
         }
@@ -878,13 +882,15 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
             clover_apply<T, G>(opaque(cs), cbase, VD, P, A);                                       // C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) sho[k][hi] = A[k];
+        } else {
+            // meanwhile the even sites form C_e r, which needs only r
+#pragma unroll
+            for (int k = 0; k < 12; k++) A[k] = she[k][hi];
+            clover_apply<T, G>(opaque(cs), cbase, VD, A, P);                                       // C_e r
         }
         __syncthreads();
         T dots[3] = {0, 0, 0};
         if (par == 0) {
-#pragma unroll
-            for (int k = 0; k < 12; k++) A[k] = she[k][hi];
-            clover_apply<T, G>(opaque(cs), cbase, VD, A, P);                                       // C_e r
             dom_hops_rolled<Sh, T, G, NLC, false>(sho, l, lbase, loc, links, P, T(0.5));   // - D_eo C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) {
