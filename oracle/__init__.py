@@ -133,8 +133,20 @@ def sap(L, b, bc, U, C, Cinv, n_cycles, n_mr, eta):
     return psi
 
 
+def sap_additive(L, b, bc, U, C, Cinv, n_cycles, n_mr, eta):
+    """Additive Schwarz (Eq. 4): all domains from the same residual each cycle."""
+    V = volume(L)
+    psi = np.empty((V, 4, 3), dtype=np.complex128)
+    st = lib().oracle_sap_additive(_i4(L), _i4(b), _d4(bc), _p(_c128(U, (V, 4, 3, 3))), _p(_c128(C, (V, 12, 12))),
+                                   _p(_c128(Cinv, (V, 12, 12))), ctypes.c_int(n_cycles), ctypes.c_int(n_mr),
+                                   _p(_c128(eta, (V, 4, 3))), _p(psi))
+    if st != OK:
+        raise ValueError(f"oracle status {st}")
+    return psi
+
+
 def fgcr(L, b, bc, U, C, Cinv, f, precond=True, n_cycles=16, n_mr=5, restart=16, tol=1e-10, max_cycles=64,
-         x0=None, history=False):
+         x0=None, history=False, additive=False):
     """Returns (x, status, n_steps, relres[, history])."""
     V = volume(L)
     f = _c128(f, (V, 4, 3))
@@ -145,7 +157,8 @@ def fgcr(L, b, bc, U, C, Cinv, f, precond=True, n_cycles=16, n_mr=5, restart=16,
     b = b if b is not None else (1, 1, 1, 1)
     Cinv = Cinv if Cinv is not None else C
     st = lib().oracle_fgcr(_i4(L), _i4(b), _d4(bc), _p(_c128(U, (V, 4, 3, 3))), _p(_c128(C, (V, 12, 12))),
-                           _p(_c128(Cinv, (V, 12, 12))), ctypes.c_int(1 if precond else 0), ctypes.c_int(n_cycles),
+                           _p(_c128(Cinv, (V, 12, 12))), ctypes.c_int((2 if additive else 1) if precond else 0),
+                           ctypes.c_int(n_cycles),
                            ctypes.c_int(n_mr), ctypes.c_int(restart), ctypes.c_double(tol), ctypes.c_int(max_cycles),
                            _p(f), _p(x), ctypes.c_int(0 if x0 is None else 1), ctypes.byref(steps), ctypes.byref(rel),
                            _p(hist))

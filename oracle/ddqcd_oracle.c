@@ -29,8 +29,8 @@
  *
  * Parity pins live in tests/ (free-field momentum-space closed form,
  * gamma5-hermiticity, gauge covariance, constant-field clover closed form,
- * D + R = A, dense block solves, dense SAP, dense LU solve, GMRES minimal
- * residual).
+ * D + R = A, dense block solves, dense SAP (multiplicative and additive),
+ * dense LU solve, GMRES minimal residual).
  */
 #include <complex.h>
 #include <math.h>
@@ -621,6 +621,42 @@ int oracle_sap(const int L[4], const int b[4], const double bc[4], const cplx *U
     return fail ? OR_ERR_NOMEM : OR_OK;
 }
 
+/* Additive Schwarz (Sec. II-D, Eq. 4): every cycle, all domains solve
+ * their block of the same residual eta - A psi, and the corrections are
+ * summed.  No colouring; psi starts at zero. */
+int oracle_sap_additive(const int L[4], const int b[4], const double bc[4], const cplx *U, const cplx *C,
+                        const cplx *Cinv, int n_cycles, int n_mr, const cplx *eta, cplx *psi)
+{
+    int e = check_domains(L, b);
+    if (e) return e;
+    build_gamma();
+    long V = volume(L);
+    long nd = V / ((long)b[0] * b[1] * b[2] * b[3]);
+    cplx *res = malloc((size_t)V * 12 * sizeof(cplx));
+    if (!res) return OR_ERR_NOMEM;
+    memset(psi, 0, (size_t)V * 12 * sizeof(cplx));
+    int fail = 0;
+    for (int s = 0; s < n_cycles; s++) {
+        oracle_apply_A(L, bc, U, C, psi, res);
+        for (long k = 0; k < V * 12; k++) res[k] = eta[k] - res[k];
+        /* domains are disjoint: each adds only to its own sites */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+        for (long d = 0; d < nd; d++) {
+            dom_t D;
+            if (dom_init(&D, L, b, U, C, Cinv, d)) { dom_free(&D); fail |= 1; continue; }
+            cplx *rl = malloc(D.n * 12 * sizeof(cplx)), *dl = malloc(D.n * 12 * sizeof(cplx));
+            for (long k = 0; k < D.n; k++) memcpy(rl + k * 12, res + (size_t)D.site[k] * 12, 12 * sizeof(cplx));
+            dom_blocksolve(&D, n_mr, rl, dl, NULL);
+            for (long k = 0; k < D.n; k++)
+                for (int c = 0; c < 12; c++) psi[(size_t)D.site[k] * 12 + c] += dl[k * 12 + c];
+            free(rl); free(dl);
+            dom_free(&D);
+        }
+    }
+    free(res);
+    return fail ? OR_ERR_NOMEM : OR_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* flexible GCR (outer solver, right preconditioning, Sec. II-C)      */
 /* ------------------------------------------------------------------ */
@@ -688,7 +724,8 @@ int oracle_fgcr(const int L[4], const int b[4], const double bc[4], const cplx *
     for (int cyc = 0; cyc < max_cycles; cyc++) {
         int kend = 0;
         for (int k = 0; k < restart; k++) {
-            if (precond) oracle_sap(L, b, bc, U, C, Cinv, n_cycles, n_mr, r, z[k]);
+            if (precond == 2) oracle_sap_additive(L, b, bc, U, C, Cinv, n_cycles, n_mr, r, z[k]);
+            else if (precond) oracle_sap(L, b, bc, U, C, Cinv, n_cycles, n_mr, r, z[k]);
             else memcpy(z[k], r, n * sizeof(cplx));
             oracle_apply_A(L, bc, U, C, z[k], w);
             for (int j = 0; j < k; j++) {

@@ -341,6 +341,57 @@ def test_sap_exact_blocks_is_block_gauss_seidel(oracle, dense_4444):
     assert rel(psi, want) < 1e-12
 
 
+def test_sap_additive_dense(oracle, dense_4444):
+    """Additive Schwarz (Eq. 4) written with dense matrices: every cycle, all
+    domains add the dense block solve of the same residual eta - A psi."""
+    g = dense_4444
+    eta = inputs.gaussian_source(g["L"], 106)
+    psi = oracle.sap_additive(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], 3, 4, eta)
+    dom, _ = R.domain_ids(g["L"], g["b"])
+    par = R.site_parity(g["L"])
+    want = np.zeros(eta.size, dtype=np.complex128)
+    for _ in range(3):
+        res = eta.reshape(-1) - g["A"] @ want
+        upd = np.zeros_like(want)
+        for d in np.unique(dom):
+            sites = np.where(dom == d)[0]
+            dof = (sites[:, None] * 12 + np.arange(12)[None]).reshape(-1)
+            upd[dof], _ = R.dense_block_solve(g["blocks"][d], np.repeat(par[sites], 12), res[dof], 4)
+        want = want + upd
+    assert rel(psi.reshape(-1), want) < 1e-13
+    # not the multiplicative method
+    mult = oracle.sap(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], 3, 4, eta)
+    assert rel(psi, mult) > 1e-3
+
+
+def test_sap_additive_exact_blocks_is_block_jacobi(oracle, dense_4444):
+    """With converged block solves, two additive cycles are two block Jacobi
+    steps: psi_1 = D^-1 eta, psi_2 = psi_1 + D^-1 (eta - A psi_1), with D the
+    block diagonal of A over all domains (solved by LAPACK)."""
+    g = dense_4444
+    eta = inputs.gaussian_source(g["L"], 107).reshape(-1)
+    psi = oracle.sap_additive(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], 2, 60, eta.reshape(-1, 4, 3)).reshape(-1)
+    dom, _ = R.domain_ids(g["L"], g["b"])
+    A = g["A"]
+    D = np.zeros_like(A)
+    for d in np.unique(dom):
+        sites = np.where(dom == d)[0]
+        dof = (sites[:, None] * 12 + np.arange(12)[None]).reshape(-1)
+        D[np.ix_(dof, dof)] = A[np.ix_(dof, dof)]
+    p1 = np.linalg.solve(D, eta)
+    p2 = p1 + np.linalg.solve(D, eta - A @ p1)
+    assert rel(psi, p2) < 1e-12
+
+
+def test_fgcr_additive_sap_dense_solve(oracle, dense_4444):
+    g = dense_4444
+    f = inputs.gaussian_source(g["L"], 108)
+    x, st, steps, relres = oracle.fgcr(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], f, precond=True, n_cycles=8,
+                                       n_mr=4, restart=16, tol=1e-12, additive=True)
+    assert st == 0 and relres <= 1e-12
+    assert rel(x.reshape(-1), np.linalg.solve(g["A"], f.reshape(-1))) < 1e-10
+
+
 def test_sap_homogeneous(oracle, dense_4444):
     g = dense_4444
     eta = inputs.gaussian_source(g["L"], 104)
