@@ -42,7 +42,7 @@ def log(*a):
 class System:
     """One lattice of the benchmark with its sources (one or more right-hand sides)."""
 
-    def __init__(self, w, U, srcs, schedule="sweeps"):
+    def __init__(self, w, U, srcs, schedule="sweeps", schwarz="multiplicative"):
         import numpy as np
         import torch
 
@@ -54,10 +54,11 @@ class System:
         self.ctx.set_solver(w.restart, w.tol, 64)
         self.ctx.set_sap(w.n_cycles, w.n_mr, w.prec)
         self.ctx.set_schedule(schedule)
+        self.ctx.set_schwarz(schwarz)
         self.b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).to(dev)
 
 
-def build(name, schedule, tune=False):
+def build(name, schedule, tune=False, schwarz="multiplicative"):
     import dataclasses
 
     import numpy as np
@@ -76,7 +77,7 @@ def build(name, schedule, tune=False):
                                             w.tol, 64, w.bc)
                 log(f"[bench] lattice {j}: domain {dom}" + (f" ({ms:.1f} ms)" if ms >= 0 else " (only fit)"))
                 w = dataclasses.replace(w, domain=dom)
-            out.append(System(w, U, [src], schedule))
+            out.append(System(w, U, [src], schedule, schwarz))
         return out
     w = configs.WORKLOADS[name]
     log(f"[bench] workload {w.name}: generating inputs")
@@ -85,7 +86,7 @@ def build(name, schedule, tune=False):
         srcs = [inputs.point_source(w.lattice, 0, s, c) for s in range(4) for c in range(3)][:w.nrhs]
     else:
         srcs = [inputs.gaussian_source(w.lattice, w.source_seed)]
-    return [System(w, U, srcs, schedule)]
+    return [System(w, U, srcs, schedule, schwarz)]
 
 
 def solve_all(systems, ddqcd):
@@ -120,6 +121,8 @@ def main():
     ap.add_argument("--schedule", default="sweeps", choices=["sweeps", "graph"],
                     help="block-solve launches issued one by one, or replayed from a captured HIP graph")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner comparison solve")
+    ap.add_argument("--schwarz", default="multiplicative", choices=["multiplicative", "additive"],
+                    help="Schwarz method of the preconditioner (the workloads are defined with multiplicative)")
     ap.add_argument("--no-tune", action="store_true",
                     help="uneven batch: keep the listed domain shapes instead of autotuning them per lattice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -136,7 +139,7 @@ def main():
     from paper_1412_2629_amd import ddqcd, geometry
 
     t_tune = time.perf_counter()
-    systems = build(args.workload, args.schedule, tune=not args.no_tune)
+    systems = build(args.workload, args.schedule, tune=not args.no_tune, schwarz=args.schwarz)
     t_tune = time.perf_counter() - t_tune
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
@@ -186,7 +189,8 @@ def main():
     for (s, _), it in zip(per_rhs, iters):
         key = (s.w.domain, s.w.prec)
         groups[key] = max(groups.get(key, 0), it)
-    launches = sum(2 * systems[0].w.n_cycles * it for it in groups.values())
+    per_call = systems[0].w.n_cycles * (1 if args.schwarz == "additive" else 2)
+    launches = sum(per_call * it for it in groups.values())
     sap_ms = sum(i["t_sap_ms"] for _, inf in runs for i in inf[:1]) / len(runs)
     launch_ms = sap_ms / launches
     achieved_tflops = flops / (sap_ms * 1e-3) / 1e12
@@ -226,13 +230,14 @@ def main():
               f"domains {'autotuned' if not args.no_tune else 'as listed'} "
               f"{[(l, d, sum(1 for s in systems if (s.w.lattice, s.w.domain) == (l, d))) for l, d in doms]}, "
               f"kappa in [0.12, 0.136], c_sw 1.5, eps in [0.3, 0.6], FP16-storage SAP {w0.n_cycles}x{w0.n_mr}, "
-              f"FGCR restart {w0.restart} (f64), tol {w0.tol}, one ddqcd_solve_batch call, schedule {args.schedule}")
+              f"FGCR restart {w0.restart} (f64), tol {w0.tol}, one ddqcd_solve_batch call, schedule {args.schedule}, "
+              f"{args.schwarz} Schwarz")
         batch = len(systems)
     else:
         wl = (f"{w0.name}: lattice {w0.lattice}, kappa {w0.kappa}, c_sw {w0.csw}, eps {w0.eps}, "
               f"domains {w0.domain}, SAP {w0.n_cycles} cycles x {w0.n_mr} MR ({w0.prec}), "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, {len(systems[0].srcs)} right-hand side(s), "
-              f"schedule {args.schedule}")
+              f"schedule {args.schedule}, {args.schwarz} Schwarz")
         batch = len(systems[0].srcs)
     out = {
         "metric": METRIC,

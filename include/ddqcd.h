@@ -65,6 +65,7 @@ typedef enum {
 typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2 } ddqcd_prec;
 
 typedef enum { DDQCD_SCHED_SWEEPS = 0, DDQCD_SCHED_QUEUE = 1, DDQCD_SCHED_GRAPH = 2 } ddqcd_schedule;
+typedef enum { DDQCD_SCHWARZ_MULTIPLICATIVE = 0, DDQCD_SCHWARZ_ADDITIVE = 1 } ddqcd_schwarz;
 
 typedef struct {
     int converged;        /* 1 if |b - A x| / |b| <= tol */
@@ -111,6 +112,16 @@ int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec);
  * switched off: selecting it returns DDQCD_ERR_ARG.  In a ddqcd_solve_batch
  * call the schedule of the first context applies. */
 int ddqcd_set_schedule(ddqcd_t ctx, int schedule);
+
+/* Which Schwarz method the preconditioner runs (Sec. II-D).
+ * DDQCD_SCHWARZ_MULTIPLICATIVE (the default, the paper's choice): each cycle
+ * visits the black domains, then the white ones, each from the residual that
+ * includes the other colour's latest corrections.  DDQCD_SCHWARZ_ADDITIVE
+ * (Eq. 4): each cycle every domain solves its block of the same residual and
+ * the corrections are summed, so one launch per cycle covers all domains
+ * (twice the block solves in flight, no colouring).  Applies to ddqcd_sap and
+ * ddqcd_solve; ddqcd_solve_batch requires it to be equal on all contexts. */
+int ddqcd_set_schwarz(ddqcd_t ctx, int kind);
 
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the
  * true relative residual |b - A x|/|b| (Sec. IV-C1), max_cycles >= 1. */

@@ -30,6 +30,8 @@ namespace {
 struct Slot {
     void *psi = nullptr, *res = nullptr, *face = nullptr, *rho_tmp = nullptr;   // block solves
     float *res_scale = nullptr, *face_scale = nullptr;
+    void *face_alt = nullptr;                                                    // additive schedule
+    float *face_scale_alt = nullptr;
     double2 *x = nullptr, *r = nullptr, *b = nullptr;                            // FP64 vectors
     double2 *Z = nullptr, *W = nullptr;                                          // FGCR basis
     int zw_restart = 0;
@@ -45,9 +47,10 @@ struct Slot {
 struct Plan {
     struct Group {
         int shape = 0, prec = 0;
-        int2 *items[2] = {nullptr, nullptr};
-        int nitems[2] = {0, 0};
+        int2 *items[3] = {nullptr, nullptr, nullptr};   // black, white, all domains
+        int nitems[3] = {0, 0, 0};
     };
+    bool additive = false;
     std::vector<Group> groups;
     SapArgs *d_args = nullptr;
     std::vector<SapArgs> h_args;
@@ -58,7 +61,7 @@ struct Plan {
         if (graph) (void)hipGraphExecDestroy(graph);
         (void)hipFree(d_args);
         for (Group &G : groups)
-            for (int c = 0; c < 2; c++) (void)hipFree(G.items[c]);
+            for (int c = 0; c < 3; c++) (void)hipFree(G.items[c]);
     }
 };
 
@@ -74,6 +77,7 @@ struct ddqcd_ctx {
     int restart = 16, max_cycles = 64;
     double tol = 1e-10;
     int schedule = DDQCD_SCHED_SWEEPS;
+    int schwarz = DDQCD_SCHWARZ_MULTIPLICATIVE;
     std::string err;
     std::vector<int> dom_host[2];   // black (0) and white (1) domains
     bool loaded = false;
@@ -197,7 +201,7 @@ struct Sys {
 // the plan depends on each system's context, slot, precision and geometry
 std::string plan_key(const std::vector<Sys> &sys)
 {
-    std::string k;
+    std::string k = sys[0].c->schwarz == DDQCD_SCHWARZ_ADDITIVE ? "A;" : "M;";
     char buf[160];
     for (const Sys &s : sys) {
         const Geo &g = s.c->g;
@@ -242,14 +246,19 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
         G.shape = gk[gi].first;
         G.prec = gk[gi].second;
         const int ndw = sap_domains_per_workgroup(G.shape, G.prec);
-        for (int col = 0; col < 2; col++) {
+        for (int col = 0; col < 3; col++) {
             // runs of ndw domains of one system (one workgroup each), one list
             // of runs per XCD; the runs of one (context, domain run) share a list
             std::vector<std::vector<std::vector<int2>>> lane(N_XCD);
             std::map<std::pair<ddqcd_t, int>, int> key_lane;
             int next = 0;
             for (int si : members[gi]) {
-                const std::vector<int> &doms = sys[si].c->dom_host[col];
+                std::vector<int> all_doms;
+                if (col == 2) {
+                    all_doms = sys[si].c->dom_host[0];
+                    all_doms.insert(all_doms.end(), sys[si].c->dom_host[1].begin(), sys[si].c->dom_host[1].end());
+                }
+                const std::vector<int> &doms = col == 2 ? all_doms : sys[si].c->dom_host[col];
                 if (doms.size() % ndw)
                     return fail(lead, DDQCD_ERR_GEOMETRY, "domain count per colour not a multiple of the workgroup's");
                 for (size_t r = 0; r * ndw < doms.size(); r++) {
@@ -273,6 +282,7 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
             HIPCHK(lead, hipMemcpy(G.items[col], items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
         }
     }
+    plan->additive = lead->schwarz == DDQCD_SCHWARZ_ADDITIVE;
     out = plan.get();
     lead->plans[key] = std::move(plan);
     return DDQCD_OK;
@@ -282,6 +292,23 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
 // then white, n_cycles times, one launch per (shape, precision) group
 hipError_t enqueue_sweeps(const Plan &plan, int n_cycles, hipStream_t s)
 {
+    if (plan.additive) {
+        // one launch per cycle over all domains; the boundary buffers alternate
+        for (int cyc = 0; cyc < n_cycles; cyc++) {
+            Visit v;
+            v.first = cyc == 0;
+            v.faces_in = cyc > 0;
+            v.last = cyc == n_cycles - 1;
+            v.faces_out = !v.last;
+            v.res_out = !v.last;
+            v.flip = cyc & 1;
+            for (const Plan::Group &G : plan.groups) {
+                hipError_t e = sap_sweep_batch(plan.d_args, G.items[2], G.nitems[2], G.shape, G.prec, v, s);
+                if (e != hipSuccess) return e;
+            }
+        }
+        return hipSuccess;
+    }
     for (int cyc = 0; cyc < n_cycles; cyc++)
         for (int col = 0; col < 2; col++) {
             Visit v;
@@ -290,6 +317,7 @@ hipError_t enqueue_sweeps(const Plan &plan, int n_cycles, hipStream_t s)
             v.last = cyc == n_cycles - 1;
             v.faces_out = !(v.last && col == 1);
             v.res_out = !v.last;
+            v.flip = 0;
             for (const Plan::Group &G : plan.groups) {
                 hipError_t e = sap_sweep_batch(plan.d_args, G.items[col], G.nitems[col], G.shape, G.prec, v, s);
                 if (e != hipSuccess) return e;
@@ -356,6 +384,15 @@ int run_sap(const std::vector<Sys> &all, const std::vector<const double2 *> &eta
         a.res_scale = sl->res_scale;
         a.face = sl->face;
         a.face_scale = sl->face_scale;
+        if (plan->additive) {
+            if (!sl->face_alt) {
+                const Geo &g = c->g;
+                if ((e = dev_alloc(c, &sl->face_alt, (size_t)g.nd * sap_face_sites(g.b) * 6 * 16))) return e;
+                if ((e = alloc(c, &sl->face_scale_alt, (size_t)g.nd * 4))) return e;
+            }
+            a.face_alt = sl->face_alt;
+            a.face_scale_alt = sl->face_scale_alt;
+        }
         a.rho_tmp = sl->rho_tmp;
         a.links = links_for(c, c->sap_prec);
         a.cs = schur_for(c, c->sap_prec);
@@ -844,6 +881,15 @@ int ddqcd_set_schedule(ddqcd_t c, int schedule)
     return DDQCD_OK;
 }
 
+int ddqcd_set_schwarz(ddqcd_t c, int kind)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (kind != DDQCD_SCHWARZ_MULTIPLICATIVE && kind != DDQCD_SCHWARZ_ADDITIVE)
+        return fail(c, DDQCD_ERR_ARG, "bad Schwarz variant");
+    c->schwarz = kind;
+    return DDQCD_OK;
+}
+
 int ddqcd_set_solver(ddqcd_t c, int restart, double tol, int max_cycles)
 {
     if (!c) return DDQCD_ERR_ARG;
@@ -984,8 +1030,9 @@ int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double
         int e = check_ready(c, "solve_batch");
         if (e) return e;
         if (c->restart != c0->restart || c->tol != c0->tol || c->max_cycles != c0->max_cycles ||
-            c->n_cycles != c0->n_cycles)
-            return fail(c, DDQCD_ERR_ARG, "batched contexts need equal solver settings and SAP cycle counts");
+            c->n_cycles != c0->n_cycles || c->schwarz != c0->schwarz)
+            return fail(c, DDQCD_ERR_ARG,
+                        "batched contexts need equal solver settings, SAP cycle counts and Schwarz variant");
         const int k = used[c]++;
         if ((e = ensure_slots(c, k + 1))) return e;
         sys.push_back({c, c->slots[k].get(), k});

@@ -37,6 +37,7 @@ struct Visit {
     int last;       // last visit: write psi to the FP64 output
     int faces_out;  // write this domain's boundary terms
     int res_out;    // store the block residual
+    int flip;       // additive schedule: which of the two boundary buffers is written
 };
 
 // Arguments of the block solves of one system (one lattice, one right-hand side).
@@ -55,6 +56,10 @@ struct SapArgs {
     float *res_scale;   // per-domain scale of res (FP16 storage)
     void *face;         // boundary half-spinors [d][8 faces][6][face sites]
     float *face_scale;  // per-domain scale of face (FP16 storage)
+    void *face_alt;     // second boundary buffer (additive schedule), else null
+    float *face_scale_alt;
+    const void *face_in;          // set in the kernel: the buffer this visit reads
+    const float *face_in_scale;
     const void *links;  // [d][mu][9 or 6][Vd]
     const void *cs;     // C_e on even / C_o^-1 on odd sites [d][36][Vd]
     void *rho_tmp;      // odd-site right-hand sides [d][12][Vd/2] when not kept in LDS

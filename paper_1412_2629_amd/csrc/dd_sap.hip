@@ -274,7 +274,7 @@ __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], in
                                             cx<T> rho[12])
 {
     constexpr int VD = Sh::VD;
-    const v2<SS> *face = (const v2<SS> *)a.face;
+    const v2<SS> *face = (const v2<SS> *)a.face_in;
     int Dn[4] = {D[0], D[1], D[2], D[3]};
     cx<T> h[6];
     if (l[MU] == 0) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], in
         bool wrap = D[MU] == 0;
         Dn[MU] = wrap ? a.g.n[MU] - 1 : D[MU] - 1;
         int dn = Dn[0] + a.g.n[0] * (Dn[1] + a.g.n[1] * (Dn[2] + a.g.n[2] * Dn[3]));
-        T sc = SCALED ? T(a.face_scale[dn]) : T(1);
+        T sc = SCALED ? T(a.face_in_scale[dn]) : T(1);
         long fb = face_base<Sh>(dn, 2 * MU + 1);
         int fi = Sh::template face_index<MU>(l);
 #pragma unroll
@@ -293,7 +293,7 @@ __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], in
         bool wrap = D[MU] == a.g.n[MU] - 1;
         Dn[MU] = wrap ? 0 : D[MU] + 1;
         int dn = Dn[0] + a.g.n[0] * (Dn[1] + a.g.n[1] * (Dn[2] + a.g.n[2] * Dn[3]));
-        T sc = SCALED ? T(a.face_scale[dn]) : T(1);
+        T sc = SCALED ? T(a.face_in_scale[dn]) : T(1);
         long fb = face_base<Sh>(dn, 2 * MU);
         int fi = Sh::template face_index<MU>(l);
 #pragma unroll
@@ -948,6 +948,28 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
     }
 }
 
+// The boundary terms a visit reads (face_in) and writes (face): one buffer for
+// the multiplicative schedule (the two colours alternate), two alternating
+// buffers for the additive one (all domains read the previous cycle's terms
+// while writing their own).
+__device__ __forceinline__ void bind_faces(SapArgs &a, const Visit &v)
+{
+    if (a.face_alt) {
+        if (v.flip) {
+            a.face_in = a.face;
+            a.face_in_scale = a.face_scale;
+            a.face = a.face_alt;
+            a.face_scale = a.face_scale_alt;
+        } else {
+            a.face_in = a.face_alt;
+            a.face_in_scale = a.face_scale_alt;
+        }
+    } else {
+        a.face_in = a.face;
+        a.face_in_scale = a.face_scale;
+    }
+}
+
 // ---- batched half-sweeps ------------------------------------------------------
 //
 // One launch covers one colour of one half-sweep for many systems (right-hand
@@ -964,8 +986,9 @@ __global__ __launch_bounds__(NDW > 1 ? Sh::VD * NDW : Sh::NT) void k_sap_lds(con
 {
     const int2 it = items[(long)blockIdx.x * NDW];
     if (it.x < 0) return;
-    const SapArgs a = args[it.x];
+    SapArgs a = args[it.x];
     if (!a.active) return;
+    bind_faces(a, v);
     int d = it.y;
     if constexpr (NDW > 1) d = items[(long)blockIdx.x * NDW + ((int)threadIdx.x & 63) / Sh::VH].y;
     lds_block_solve<Sh, NDW, T, SS, PS, G, NLC, LNLC, SCALED, LINK_LDS, CL_REG>(a, d, v);
@@ -976,8 +999,9 @@ __global__ __launch_bounds__(Sh::VD) void k_sap_f64(const SapArgs *args, const i
 {
     const int2 it = items[blockIdx.x];
     if (it.x < 0) return;
-    const SapArgs a = args[it.x];
+    SapArgs a = args[it.x];
     if (!a.active) return;
+    bind_faces(a, v);
     f64_block_solve<Sh>(a, it.y, v);
 }
 
@@ -988,6 +1012,7 @@ __global__ __launch_bounds__(Sh::VH) void k_sap_sweep(const SapArgs *args, const
     if (it.x < 0) return;
     SapArgs a = args[it.x];
     if (!a.active) return;
+    bind_faces(a, v);
     a.first = v.first;
     a.faces_in = v.faces_in;
     a.last = v.last;
@@ -1056,6 +1081,8 @@ __device__ __forceinline__ bool wait_neighbours(const QueueArgs &q, const Geo &g
 template <class Sh, typename SS, typename G, bool SCALED>
 __global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
 {
+    a.face_in = a.face;
+    a.face_in_scale = a.face_scale;
     __shared__ int task_s, ok_s;
     const int ntask = q.n_cycles * q.nd;
     for (;;) {

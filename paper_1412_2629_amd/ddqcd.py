@@ -17,7 +17,8 @@ PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP1
 
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 
-EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_solver", "ddqcd_load_gauge",
+EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
+           "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_tune_domain", "ddqcd_last_error",
            "ddqcd_status_string"]
 
@@ -52,6 +53,7 @@ def lib():
         L.ddqcd_set_sap.argtypes = [vp, i, i, i]
         L.ddqcd_set_solver.argtypes = [vp, i, d, i]
         L.ddqcd_set_schedule.argtypes = [vp, i]
+        L.ddqcd_set_schwarz.argtypes = [vp, i]
         L.ddqcd_load_gauge.argtypes = [vp, vp, vp]
         L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
         L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
@@ -127,6 +129,11 @@ class Context:
         from a captured HIP graph) or "queue" (persistent work-queue kernel, switched off)."""
         mode = {"sweeps": SCHED_SWEEPS, "queue": SCHED_QUEUE, "graph": SCHED_GRAPH}.get(schedule, schedule)
         self._check(lib().ddqcd_set_schedule(self._h, mode), "set_schedule")
+
+    def set_schwarz(self, kind):
+        """"multiplicative" (the default) or "additive" Schwarz preconditioner."""
+        mode = {"multiplicative": 0, "additive": 1}.get(kind, kind)
+        self._check(lib().ddqcd_set_schwarz(self._h, mode), "set_schwarz")
 
     def set_solver(self, restart=16, tol=1e-10, max_cycles=64):
         self._check(lib().ddqcd_set_solver(self._h, restart, ctypes.c_double(tol), max_cycles), "set_solver")

@@ -64,6 +64,9 @@ def test_create_settings_and_state_errors():
         assert L.ddqcd_set_sap(h, 16, 5, 7) == ddqcd.ERR_ARG
         assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16) == ddqcd.OK
         assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP64) == ddqcd.OK
+        assert L.ddqcd_set_schwarz(h, 2) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_schwarz(h, 1) == ddqcd.OK
+        assert L.ddqcd_set_schwarz(h, 0) == ddqcd.OK
         assert L.ddqcd_set_solver(h, 0, 1e-10, 10) == ddqcd.ERR_ARG
         assert L.ddqcd_set_solver(h, 17, 1e-10, 10) == ddqcd.ERR_ARG
         assert L.ddqcd_set_solver(h, 16, 0.0, 10) == ddqcd.ERR_ARG

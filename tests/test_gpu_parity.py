@@ -212,3 +212,71 @@ def test_fp64_sap_rejected_on_padded_domains():
     with pytest.raises(ddqcd.DDQCDError) as e:
         ctx.set_sap(4, 5, "f64")
     assert e.value.status == ddqcd.ERR_GEOMETRY
+
+
+# ---------------------------------------------------------------------------
+# additive Schwarz (Eq. 4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", SMALL, ids=repr)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_sap_additive(case, prec, oracle):
+    if prec == "f64" and not fp64_sap(case):
+        pytest.skip(NO_FP64_SAP)
+    eta = case.source(15)
+    want = oracle.sap_additive(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
+    ctx = case.context(prec)
+    ctx.set_schwarz("additive")
+    got = host(ctx.sap(dev(eta)))
+    err = rel(got, want)
+    tol = 1e-12 if prec == "f64" else SAP_TOL[prec] * case.n_cycles
+    print(f"{case} additive SAP {prec} error {err:.3e} (bound {tol:.2e})")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[2], SMALL[3], SMALL[5]], ids=repr)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_solve_additive(case, prec, oracle):
+    f = case.source(16)
+    x_or, st, steps, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                     n_mr=case.n_mr, restart=16, tol=1e-12, additive=True)
+    assert st == 0
+    ctx = case.context(prec)
+    ctx.set_schwarz("additive")
+    ctx.set_solver(16, 1e-10, 64)
+    x, info, status = ctx.solve(dev(f))
+    x = host(x)
+    true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+    err = rel(x, x_or)
+    print(f"{case} additive {prec}: steps {info[0]['iters']} (oracle fp64 {steps}), true residual {true_res:.2e}, "
+          f"solution error {err:.2e}")
+    assert status == 0 and true_res <= 1e-10 and err <= 1e-8
+
+
+def test_additive_graph_and_batch():
+    """Graph replays of the additive launches equal the eager ones bit for bit;
+    batched additive solves equal single ones; mixed Schwarz variants in one
+    batch are rejected."""
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[2]
+    ctx = case.context("f16")
+    ctx.set_schwarz("additive")
+    eta = dev(case.source(17))
+    eager = host(ctx.sap(eta))
+    ctx.set_schedule("graph")
+    for _ in range(3):
+        assert np.array_equal(host(ctx.sap(eta)), eager)
+        ctx.apply_D(eta, "f64")
+    ctx.set_schedule("sweeps")
+    other = SMALL[3].context("f32")
+    other.set_sap(case.n_cycles, 5, "f32")
+    other.set_schwarz("additive")
+    fa, fb = dev(case.source(18)), dev(SMALL[3].source(19))
+    xs, infos, st = ddqcd.solve_batch([ctx, other], [fa, fb])
+    assert st == ddqcd.OK
+    x1, _, _ = ctx.solve(fa)
+    assert np.array_equal(host(x1), host(xs[0]))
+    other.set_schwarz("multiplicative")
+    with pytest.raises(ddqcd.DDQCDError) as e:
+        ddqcd.solve_batch([ctx, other], [fa, fb])
+    assert e.value.status == ddqcd.ERR_ARG
