@@ -32,7 +32,7 @@ CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 # they were taken on, identified by a hash; after any change to those sources
 # the figure is reported as null until it is measured again.
 KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
-MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.36e6, "sources": "a166705087465ae1"}}
+MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.49e6, "sources": "b447b341524edff8"}}
 
 
 def log(*a):
@@ -220,6 +220,20 @@ def main():
                 "speedup_mixed_over_fp64": round(t64 / t_solve, 3),
                 "rel_diff_mixed_vs_fp64_solution": diff}
 
+    # the solver without domain decomposition (FP64 BiCGstab) on the same GPU
+    nodd = None
+    if not args.no_fp64 and len(systems) == 1 and len(systems[0].srcs) == 1:
+        log("[bench] non-DD comparison solve (FP64 BiCGstab)")
+        s = systems[0]
+        s.ctx.solve_bicgstab(s.b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xb, ib, stb = s.ctx.solve_bicgstab(s.b)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t1
+        nodd = {"bicgstab_fp64_solve_s": round(tb, 5), "bicgstab_iters": ib["iters"],
+                "converged": bool(ib["converged"]), "speedup_dd_over_non_dd": round(tb / t_solve, 3)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(systems, iters)
@@ -266,6 +280,7 @@ def main():
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)"},
         "mixed_vs_fp64": fp64,
+        "dd_vs_non_dd": nodd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

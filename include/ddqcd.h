@@ -169,6 +169,20 @@ int ddqcd_solve(ddqcd_t ctx, double *x, const double *b, int nrhs, int x_is_gues
 int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double *const *b, int x_is_guess,
                       ddqcd_info *info, void *stream);
 
+/* Solves A x = b (one right-hand side, canonical layouts, device pointers) with
+ * BiCGstab in FP64 on the full operator and no preconditioner: the solver
+ * without domain decomposition that the paper measures its method against
+ * (Sec. IV-C: double-precision BiCGstab).  The same stopping rule as
+ * ddqcd_solve (true relative residual <= the tol of ddqcd_set_solver; a
+ * recursive residual below tol is confirmed with b - A x, and the iteration
+ * restarts from it if not met).  At most max_iter iterations (each two
+ * applications of A).  info (optional) receives iters, restarts,
+ * rel_residual, converged and t_total_ms.  Returns DDQCD_OK,
+ * DDQCD_ERR_NOT_CONVERGED (x holds the last iterate) or DDQCD_ERR_NONFINITE
+ * on breakdown. */
+int ddqcd_solve_bicgstab(ddqcd_t ctx, double *x, const double *b, int x_is_guess, int max_iter, ddqcd_info *info,
+                         void *stream);
+
 /* Picks a domain shape for a lattice.  The domain size trades the number of
  * independent block solves per half-sweep (Sec. IV-B2's n_domain, the
  * parallelism) against the strength of the preconditioner (larger blocks,

@@ -178,15 +178,16 @@ int ensure_slots(ddqcd_t c, int n)
     return DDQCD_OK;
 }
 
-int ensure_basis(ddqcd_t c, Slot &sl)
+int ensure_basis(ddqcd_t c, Slot &sl, int columns = 0)
 {
-    if (sl.zw_restart >= c->restart) return DDQCD_OK;
+    const int want = std::max(columns, c->restart);
+    if (sl.zw_restart >= want) return DDQCD_OK;
     const size_t nc = (size_t)ncomplex(c->g);
     int e;
     // grow the basis (a smaller old one stays owned until destroy)
-    if ((e = alloc(c, &sl.Z, nc * 16 * c->restart))) return e;
-    if ((e = alloc(c, &sl.W, nc * 16 * c->restart))) return e;
-    sl.zw_restart = c->restart;
+    if ((e = alloc(c, &sl.Z, nc * 16 * want))) return e;
+    if ((e = alloc(c, &sl.W, nc * 16 * want))) return e;
+    sl.zw_restart = want;
     return DDQCD_OK;
 }
 
@@ -776,6 +777,103 @@ int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *c
     return st;
 }
 
+// BiCGstab (van der Vorst 1992) on A in FP64, no preconditioner: the solver
+// without domain decomposition that the paper compares against (Sec. IV-C).
+// x and b are the slot's internal vectors; work vectors are basis columns.
+int bicgstab(ddqcd_t c, Slot &sl, bool guess, int max_iter, ddqcd_info &info, hipStream_t s)
+{
+    const long n = ncomplex(c->g);
+    int e;
+    if ((e = ensure_basis(c, sl, 5))) return e;
+    double2 *r0 = sl.Z, *p = sl.Z + n, *v = sl.Z + 2 * n, *sv = sl.Z + 3 * n, *t = sl.Z + 4 * n;
+    double2 *x = sl.x, *r = sl.r, *b = sl.b;
+    double2 h[2];
+    auto fetch = [&](int m) -> int {
+        HIPCHK(c, hipMemcpyAsync(h, sl.blas.result, sizeof(double2) * m, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return DDQCD_OK;
+    };
+    auto dot = [&](const double2 *a, const double2 *bb, C &out) -> int {   // <a, bb>
+        HIPCHK(c, multidot(sl.blas, a, n, 1, bb, n, s));
+        int e2 = fetch(1);
+        out = C(h[0].x, h[0].y);
+        return e2;
+    };
+    const double2 one = make_double2(1, 0), zero2 = make_double2(0, 0);
+    auto cd = [](C z) { return make_double2(z.real(), z.imag()); };
+    if (!guess) HIPCHK(c, zero(x, n, s));
+    HIPCHK(c, norm2(sl.blas, b, n, s));
+    if ((e = fetch(1))) return e;
+    const double bn = std::sqrt(h[0].x);
+    info = ddqcd_info{};
+    if (!std::isfinite(bn)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite right-hand side");
+    if (bn == 0) {
+        HIPCHK(c, zero(x, n, s));
+        info.converged = 1;
+        return DDQCD_OK;
+    }
+    // r = b - A x, r0 = r, p = v = 0
+    if ((e = apply_A64(c, x, r, s))) return e;
+    HIPCHK(c, residual(sl.blas, b, r, n, s));
+    if ((e = fetch(1))) return e;
+    double rel = std::sqrt(h[0].x) / bn;
+    HIPCHK(c, lincomb(r0, r, one, r, zero2, nullptr, zero2, n, s));
+    HIPCHK(c, zero(p, n, s));
+    HIPCHK(c, zero(v, n, s));
+    C rho_old = 1, alpha = 1, omega = 1;
+    int it = 0, restarts = 0;
+    while (rel > c->tol && it < max_iter) {
+        C rho;
+        if ((e = dot(r0, r, rho))) return e;
+        if (std::abs(rho) == 0 || std::abs(omega) == 0) return fail(c, DDQCD_ERR_NONFINITE, "BiCGstab breakdown");
+        const C beta = (rho / rho_old) * (alpha / omega);
+        // p = r + beta (p - omega v)
+        HIPCHK(c, lincomb(p, r, one, p, cd(beta), v, cd(-beta * omega), n, s));
+        if ((e = apply_A64(c, p, v, s))) return e;
+        C r0v;
+        if ((e = dot(r0, v, r0v))) return e;
+        alpha = rho / r0v;
+        // s = r - alpha v, t = A s, omega = <t, s> / <t, t>
+        HIPCHK(c, lincomb(sv, r, one, v, cd(-alpha), nullptr, zero2, n, s));
+        if ((e = apply_A64(c, sv, t, s))) return e;
+        HIPCHK(c, dot2(sl.blas, t, sv, n, s));
+        if ((e = fetch(2))) return e;
+        omega = h[1].x > 0 ? C(h[0].x, h[0].y) / h[1].x : C(0);
+        // x += alpha p + omega s, r = s - omega t
+        HIPCHK(c, lincomb(x, x, one, p, cd(alpha), sv, cd(omega), n, s));
+        HIPCHK(c, lincomb(r, sv, one, t, cd(-omega), nullptr, zero2, n, s));
+        HIPCHK(c, norm2(sl.blas, r, n, s));
+        if ((e = fetch(1))) return e;
+        rel = std::sqrt(h[0].x) / bn;
+        rho_old = rho;
+        it++;
+        if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
+        if (rel <= c->tol) {
+            // confirm with the true residual; restart from it if the recursion drifted
+            if ((e = apply_A64(c, x, r, s))) return e;
+            HIPCHK(c, residual(sl.blas, b, r, n, s));
+            if ((e = fetch(1))) return e;
+            rel = std::sqrt(h[0].x) / bn;
+            if (rel > c->tol) {
+                restarts++;
+                HIPCHK(c, lincomb(r0, r, one, r, zero2, nullptr, zero2, n, s));
+                HIPCHK(c, zero(p, n, s));
+                HIPCHK(c, zero(v, n, s));
+                rho_old = alpha = omega = 1;
+            }
+        }
+    }
+    info.converged = rel <= c->tol;
+    info.iters = it;
+    info.restarts = restarts;
+    info.rel_residual = rel;
+    if (!info.converged) {
+        c->err = "BiCGstab not converged: relative residual " + std::to_string(rel);
+        return DDQCD_ERR_NOT_CONVERGED;
+    }
+    return DDQCD_OK;
+}
+
 bool is_pm1(double v) { return v == 1.0 || v == -1.0; }
 
 }  // namespace
@@ -1038,6 +1136,28 @@ int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double
         sys.push_back({c, c->slots[k].get(), k});
     }
     return solve_systems(sys, x, b, x_is_guess, info, (hipStream_t)stream);
+}
+
+int ddqcd_solve_bicgstab(ddqcd_t c, double *x, const double *b, int x_is_guess, int max_iter, ddqcd_info *info,
+                         void *stream)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (!x || !b || x == b || max_iter < 1) return fail(c, DDQCD_ERR_ARG, "bad bicgstab arguments");
+    int e = check_ready(c, "solve_bicgstab");
+    if (e || (e = ensure_slots(c, 1))) return e;
+    hipStream_t s = (hipStream_t)stream;
+    Slot &sl = *c->slots[0];
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(c, import_spinor(c->g, b, sl.b, P64, s));
+    if (x_is_guess) HIPCHK(c, import_spinor(c->g, x, sl.x, P64, s));
+    ddqcd_info inf{};
+    const int st = bicgstab(c, sl, x_is_guess != 0, max_iter, inf, s);
+    if (st != DDQCD_OK && st != DDQCD_ERR_NOT_CONVERGED) return st;
+    HIPCHK(c, export_spinor(c->g, sl.x, P64, x, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    inf.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return st;
 }
 
 int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,

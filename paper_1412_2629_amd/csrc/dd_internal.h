@@ -117,5 +117,10 @@ hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s
 // result[0] = (|v|^2, 0)
 hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s);
 hipError_t zero(double2 *v, long n, hipStream_t s);
+// result[0] = <t, s>, result[1] = (|t|^2, 0)
+hipError_t dot2(Blas &B, const double2 *t, const double2 *s_vec, long n, hipStream_t s);
+// out = ca a + cb b + cc c; c may be null; out may alias an input
+hipError_t lincomb(double2 *out, const double2 *a, double2 ca, const double2 *b, double2 cb, const double2 *c,
+                   double2 cc, long n, hipStream_t s);
 
 }  // namespace dd

@@ -647,6 +647,51 @@ hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s)
     return hipGetLastError();
 }
 
+// result[0] = <t, s>, result[1] = (|t|^2, 0)
+__global__ __launch_bounds__(BS) void k_dot2(const double2 *t, const double2 *sv, long n, double2 *partial)
+{
+    double acc[4] = {0, 0, 0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const double2 a = t[i], b = sv[i];
+        acc[0] += a.x * b.x + a.y * b.y;
+        acc[1] += a.x * b.y - a.y * b.x;
+        acc[2] += a.x * a.x + a.y * a.y;
+    }
+    block_reduce_store<4>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t dot2(Blas &B, const double2 *t, const double2 *sv, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot2, blas_blocks(n), BS, 0, s, t, sv, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 2, B.result);
+    return hipGetLastError();
+}
+
+// out = ca a + cb b + cc c (complex coefficients; c may be null; out may alias a, b or c)
+__global__ __launch_bounds__(BS) void k_lincomb(double2 *out, const double2 *a, double2 ca, const double2 *b,
+                                                double2 cb, const double2 *c, double2 cc, long n)
+{
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const double2 x = a[i], y = b[i];
+        double2 o;
+        o.x = ca.x * x.x - ca.y * x.y + cb.x * y.x - cb.y * y.y;
+        o.y = ca.x * x.y + ca.y * x.x + cb.x * y.y + cb.y * y.x;
+        if (c) {
+            const double2 z = c[i];
+            o.x += cc.x * z.x - cc.y * z.y;
+            o.y += cc.x * z.y + cc.y * z.x;
+        }
+        out[i] = o;
+    }
+}
+
+hipError_t lincomb(double2 *out, const double2 *a, double2 ca, const double2 *b, double2 cb, const double2 *c,
+                   double2 cc, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lincomb, blas_blocks(n), BS, 0, s, out, a, ca, b, cb, c, cc, n);
+    return hipGetLastError();
+}
+
 __global__ void k_zero(double2 *v, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)

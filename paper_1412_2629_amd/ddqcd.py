@@ -19,7 +19,8 @@ SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
            "ddqcd_set_solver", "ddqcd_load_gauge",
-           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_tune_domain", "ddqcd_last_error",
+           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
+           "ddqcd_last_error",
            "ddqcd_status_string"]
 
 
@@ -60,6 +61,7 @@ def lib():
         L.ddqcd_solve.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
         L.ddqcd_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp), i,
                                         ctypes.POINTER(Info), vp]
+        L.ddqcd_solve_bicgstab.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
         L.ddqcd_tune_domain.argtypes = [ctypes.POINTER(i), d, d, ctypes.POINTER(d), vp, vp, i, i, i, i, d, i,
                                         ctypes.POINTER(i), ctypes.POINTER(d), vp]
         L.ddqcd_last_error.argtypes = [vp]
@@ -160,6 +162,17 @@ class Context:
         out = torch.empty_like(eta) if out is None else out
         self._check(lib().ddqcd_sap(self._h, _ptr(out, "out"), _ptr(eta, "in"), self._nrhs(eta), _stream()), "sap")
         return out
+
+    def solve_bicgstab(self, b, x0=None, max_iter=20000, check=True):
+        """FP64 BiCGstab without preconditioner (one right-hand side).  Returns (x, info dict, status)."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = Info()
+        st = lib().ddqcd_solve_bicgstab(self._h, _ptr(x, "x"), _ptr(b, "b"), 0 if x0 is None else 1, max_iter,
+                                        ctypes.byref(info), _stream())
+        if check and st not in (OK, ERR_NOT_CONVERGED):
+            self._check(st, "solve_bicgstab")
+        return x, info.as_dict(), st
 
     def solve(self, b, x0=None, check=True):
         """Returns (x, [info dicts], status)."""

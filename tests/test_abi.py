@@ -79,6 +79,9 @@ def test_create_settings_and_state_errors():
         assert L.ddqcd_sap(h, dummy, dummy2, 1, None) == ddqcd.ERR_STATE
         assert L.ddqcd_solve(h, dummy, dummy2, 1, 0, None, None) == ddqcd.ERR_STATE
         assert b"load_gauge" in L.ddqcd_last_error(h)
+        assert L.ddqcd_solve_bicgstab(h, dummy, dummy2, 0, 100, None, None) == ddqcd.ERR_STATE
+        assert L.ddqcd_solve_bicgstab(h, dummy, dummy, 0, 100, None, None) == ddqcd.ERR_ARG    # aliasing
+        assert L.ddqcd_solve_bicgstab(h, dummy, dummy2, 0, 0, None, None) == ddqcd.ERR_ARG     # max_iter
         # argument errors
         assert L.ddqcd_apply_D(h, dummy, dummy, 1, 0, None) == ddqcd.ERR_ARG      # aliasing
         assert L.ddqcd_apply_D(h, dummy, dummy2, 0, 0, None) == ddqcd.ERR_ARG     # nrhs

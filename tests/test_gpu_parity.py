@@ -280,3 +280,30 @@ def test_additive_graph_and_batch():
     with pytest.raises(ddqcd.DDQCDError) as e:
         ddqcd.solve_batch([ctx, other], [fa, fb])
     assert e.value.status == ddqcd.ERR_ARG
+
+
+# ---------------------------------------------------------------------------
+# the solver without domain decomposition (FP64 BiCGstab, Sec. IV-C)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[2], SMALL[3]], ids=repr)
+def test_bicgstab(case, oracle):
+    f = case.source(20)
+    x_or, st, _, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                 n_mr=case.n_mr, restart=16, tol=1e-12)
+    assert st == 0
+    ctx = case.context()
+    ctx.set_solver(16, 1e-10, 64)
+    x, info, status = ctx.solve_bicgstab(dev(f))
+    x = host(x)
+    true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+    err = rel(x, x_or)
+    print(f"{case} BiCGstab: {info['iters']} iterations, {info['restarts']} restarts, true residual {true_res:.2e}, "
+          f"solution error {err:.2e}")
+    assert status == 0 and info["converged"] == 1
+    assert true_res <= 1e-10 and abs(info["rel_residual"] - true_res) <= 1e-12 and err <= 1e-8
+    # zero source and exact guess
+    z, info0, st0 = ctx.solve_bicgstab(dev(np.zeros_like(f)))
+    assert st0 == 0 and info0["iters"] == 0 and not np.any(host(z))
+    x2, info2, st2 = ctx.solve_bicgstab(dev(f), x0=dev(x))
+    assert st2 == 0 and info2["iters"] == 0
