@@ -17,7 +17,7 @@ def declared():
     return sorted(set(re.findall(r"\b(ddqcd_[A-Za-z_0-9]+)\s*\(", txt)))
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_the_solver_calls():
     names = declared()
     for n in ["ddqcd_create", "ddqcd_load_gauge", "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve"]:
         assert n in names
