@@ -359,7 +359,14 @@ template <typename T, typename SI, typename SO, typename G, int NLC>
 __global__ __launch_bounds__(256) void k_apply_A(Geo g, const v2<SI> *in, v2<SO> *out, const v2<G> *links,
                                                  const v2<G> *clov)
 {
-    long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    // Workgroup w runs on XCD w mod 8.  Blocks are handed out so that each
+    // XCD sweeps one contiguous eighth of the domain-blocked site order: most
+    // neighbour spinors and links a workgroup reads were brought into the
+    // same XCD's L2 by its neighbours (a plain order spreads neighbouring
+    // blocks over all eight L2s).
+    const unsigned nbk = gridDim.x, w = blockIdx.x;
+    const unsigned blk = nbk % 8 == 0 ? (w % 8) * (nbk / 8) + w / 8 : w;
+    long I = (long)blk * blockDim.x + threadIdx.x;
     if (I >= g.V) return;
     int x[4], d, loc;
     decode(g, I, x, d, loc);

@@ -163,3 +163,31 @@ def test_tune_domain_picks_a_converging_shape():
     ctx.set_sap(4, 5, "f16")
     x, info, st = ctx.solve(f)
     assert st == ddqcd.OK
+
+
+def test_tune_domain_respects_precision():
+    """12x12x4x8 is tiled by 2^4 and by 6x6x2x4; 6x6x2x4 has no FP64 kernel,
+    so an FP64 tuning returns 2^4 untimed while FP16 times both."""
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[5]
+    f = dev(case.source(96))
+    dom, ms = ddqcd.tune_domain(case.L, case.kappa, case.csw, dev(case.U), f, prec="f64", n_cycles=4, n_mr=5)
+    assert dom == (2, 2, 2, 2) and ms == -1
+    dom, ms = ddqcd.tune_domain(case.L, case.kappa, case.csw, dev(case.U), f, prec="f16", n_cycles=4, n_mr=5)
+    assert dom in ((2, 2, 2, 2), (6, 6, 2, 4)) and ms > 0
+
+
+def test_graph_batch_with_fp64_systems(oracle):
+    from paper_1412_2629_amd import ddqcd
+    a = SMALL[0].context()
+    a.set_sap(4, 4, "f64")
+    b = SMALL[2].context()
+    b.set_sap(4, 5, "f64")
+    fs = [dev(SMALL[0].source(97)), dev(SMALL[2].source(98))]
+    xs, infos, st = ddqcd.solve_batch([a, b], fs)
+    a.set_schedule("graph")
+    xg, infog, stg = ddqcd.solve_batch([a, b], fs)
+    assert st == stg == ddqcd.OK
+    for c, x, y, f in zip((SMALL[0], SMALL[2]), xs, xg, fs):
+        assert np.array_equal(host(x), host(y))
+        assert rel(oracle.apply_A(c.L, BC, c.U, c.C, host(x)), host(f)) <= 1e-10
