@@ -233,6 +233,43 @@ __device__ __forceinline__ void dom_hops(const cx<T> (*v)[Sh::VH], const int l[4
     dom_hop<Sh, 3, T, G, NLC>(v, l, lbase, loc, links, acc);
 }
 
+// The hop sum of every site of parity po, shared by the site's thread pair:
+// the thread of parity po takes directions 0 and 1 of its own site, the thread
+// of the other parity with the same half index takes directions 2 and 3 of
+// that site (partner coordinates lp, index locp) and hands its partial sum over
+// through X ([12][VH] in LDS).  XFREE: nothing reads X during the hops, so the
+// partial is written at once; otherwise after a barrier.  Every thread of the
+// workgroup calls this (it holds barriers); on return the po thread's acc is
+// the whole sum, the other thread's acc is its own partial.
+template <class Sh, typename T, typename G, int NLC, bool XFREE>
+__device__ __forceinline__ void pair_hops(const cx<T> (*v)[Sh::VH], cx<T> (*X)[Sh::VH], int po, int par, int hi,
+                                          const int l[4], int loc, const int lp[4], int locp, long lbase,
+                                          const v2<G> *links, cx<T> acc[12])
+{
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = czero<T>();
+    if (par == po) {
+        dom_hop<Sh, 0, T, G, NLC>(v, l, lbase, loc, links, acc);
+        dom_hop<Sh, 1, T, G, NLC>(v, l, lbase, loc, links, acc);
+    } else if (par == 1 - po) {
+        dom_hop<Sh, 2, T, G, NLC>(v, lp, lbase, locp, links, acc);
+        dom_hop<Sh, 3, T, G, NLC>(v, lp, lbase, locp, links, acc);
+        if constexpr (XFREE)
+#pragma unroll
+            for (int k = 0; k < 12; k++) X[k][hi] = acc[k];
+    }
+    if constexpr (!XFREE) {
+        __syncthreads();
+        if (par == 1 - po)
+#pragma unroll
+            for (int k = 0; k < 12; k++) X[k][hi] = acc[k];
+    }
+    __syncthreads();
+    if (par == po)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = acc[k] + X[k][hi];
+}
+
 // A uniform pointer the compiler must treat as unknown from here on: the
 // addresses derived from it are formed at their use instead of being
 // precomputed and held in registers across loops.
@@ -598,6 +635,11 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     cx<T>(*sho)[VH] = sho_all[sub];
     int l[4];
     Sh::coords(loc, l);
+    // the site of the other parity with the same half index: its hops in
+    // directions 2 and 3 are this thread's share of its hop sums
+    const int locp = (1 - par) * VH + hi;
+    int lp[4];
+    Sh::coords(par < 2 ? locp : loc, lp);
     int D[4];
     {
         int r = d;
@@ -673,9 +715,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     }
     __syncthreads();   // also publishes slink
     // the even-site MR residual r lives in its own slot of she for the whole
-    // solve (fewer live registers); x stays in the registers of A
+    // solve (fewer live registers); x stays in the registers of A.  she is
+    // free until r is written, so it carries the odd threads' partial sums.
+    pair_hops<Sh, T, G, HNLC, true>(sho, she, 0, par, hi, l, loc, lp, locp, lbase, links, P);
     if (par == 0) {
-        dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, P);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             she[k][hi] = A[k] + scal(T(0.5), P[k]);
@@ -694,9 +737,11 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
             for (int q = 0; q < 36; q++) asm volatile("" : "+v"(cl[q]));
         }
         __syncthreads();
+        // sho is dead here (its last readers passed the reduction's barriers),
+        // so it carries the even threads' partial sums
+        cx<T> t[12];
+        pair_hops<Sh, T, G, HNLC, true>(she, sho, 1, par, hi, l, loc, lp, locp, lbase, links, t);
         if (par == 1) {
-            cx<T> t[12];
-            dom_hops<Sh, T, G, HNLC>(she, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) t[k] = scal(T(-0.5), t[k]);   // D_oe r
             clover(t, P);                                // C_o^-1 D_oe r
@@ -711,9 +756,8 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         }
         __syncthreads();
         T dots[3] = {0, 0, 0};
+        pair_hops<Sh, T, G, HNLC, false>(sho, sho, 0, par, hi, l, loc, lp, locp, lbase, links, t);
         if (par == 0) {
-            cx<T> t[12];
-            dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, t);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<T> rk = she[k][hi];
@@ -741,12 +785,14 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
         for (int k = 0; k < 12; k++) sho[k][hi] = A[k];
     __syncthreads();
-    if (par == 1) {
+    {
         cx<T> t[12];
-        dom_hops<Sh, T, G, HNLC>(sho, l, lbase, loc, links, t);
+        pair_hops<Sh, T, G, HNLC, false>(sho, sho, 1, par, hi, l, loc, lp, locp, lbase, links, t);
+        if (par == 1) {
 #pragma unroll
-        for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
-        clover(t, A);
+            for (int k = 0; k < 12; k++) t[k] = A[k] + scal(T(0.5), t[k]);
+            clover(t, A);
+        }
     }
 
     // ---- epilogue
