@@ -28,11 +28,12 @@ CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 
 # HBM bytes per half-sweep launch of the block-solve kernel, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes calibrated against a plain device copy
-# (profiles/k_sap_lds_16x16x16x32_f32.md).  They hold for the kernel sources
+# (profiles/k_sap_lds_16x16x16x32_f32.md, profiles/k_sap_lds_32x32x32x64_f16_and_uneven_batch.md).  They hold for the kernel sources
 # they were taken on, identified by a hash; after any change to those sources
 # the figure is reported as null until it is measured again.
 KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
-MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 68.49e6, "sources": "b447b341524edff8"}}
+MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 67.63e6, "sources": "a96bf007c59536d5"},
+                    "C3": {"bytes_per_launch": 664.15e6, "sources": "a96bf007c59536d5"}}
 
 
 def log(*a):

@@ -301,6 +301,50 @@ __device__ __forceinline__ void dom_hops_rolled(const cx<T> (*v)[Sh::VH], const 
     }
 }
 
+// pair_hops with the directions visited in a loop that is not unrolled and a
+// scale: the po thread's acc (zeroed first if ZERO) gains scale x its share
+// and then the helper's; the helper's acc is zeroed and takes its share.
+template <class Sh, typename T, typename G, int NLC, bool XFREE, bool ZERO>
+__device__ __forceinline__ void pair_hops_rolled(const cx<T> (*v)[Sh::VH], cx<T> (*X)[Sh::VH], int po, int par,
+                                                 int hi, const int l[4], int loc, const int lp[4], int locp,
+                                                 long lbase, const v2<G> *links, cx<T> acc[12], T scale)
+{
+    const bool own = par == po, help = par == 1 - po;
+    if (ZERO || !own)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = czero<T>();
+    if (own || help) {
+        int ls[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) ls[q] = own ? l[q] : lp[q];
+        const int ss = own ? loc : locp;
+#pragma unroll 1
+        for (int mu = own ? 0 : 2; mu < (own ? 2 : 4); mu++) {
+            const v2<G> *lk = opaque(links);
+            switch (mu) {
+                case 0: dom_hop<Sh, 0, T, G, NLC>(v, ls, lbase, ss, lk, acc, scale); break;
+                case 1: dom_hop<Sh, 1, T, G, NLC>(v, ls, lbase, ss, lk, acc, scale); break;
+                case 2: dom_hop<Sh, 2, T, G, NLC>(v, ls, lbase, ss, lk, acc, scale); break;
+                default: dom_hop<Sh, 3, T, G, NLC>(v, ls, lbase, ss, lk, acc, scale); break;
+            }
+        }
+    }
+    if constexpr (XFREE) {
+        if (help)
+#pragma unroll
+            for (int k = 0; k < 12; k++) X[k][hi] = acc[k];
+    } else {
+        __syncthreads();
+        if (help)
+#pragma unroll
+            for (int k = 0; k < 12; k++) X[k][hi] = acc[k];
+    }
+    __syncthreads();
+    if (own)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = acc[k] + X[k][hi];
+}
+
 // ---- boundary terms --------------------------------------------------------
 
 template <class Sh> __device__ __forceinline__ long face_base(int d, int f) { return ((long)d * Sh::FTOT + Sh::foff(f)) * 6; }
@@ -865,6 +909,11 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
     const int hi = loc - par * VH;
     int l[4];
     Sh::coords(loc, l);
+    // the site of the other parity with the same half index (its hops in
+    // directions 2 and 3 are this thread's share)
+    const int locp = (1 - par) * VH + hi;
+    int lp[4];
+    Sh::coords(locp, lp);
     int D[4];
     {
         int r = d;
@@ -910,11 +959,12 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
         }
     }
     __syncthreads();
+    // she is free until r is written: it carries the odd threads' partial sums
+    pair_hops_rolled<Sh, T, G, NLC, true, true>(sho, she, 0, par, hi, l, loc, lp, locp, lbase, links, P, T(0.5));
     if (par == 0) {
-        dom_hops_rolled<Sh, T, G, NLC, false>(sho, l, lbase, loc, links, A, T(0.5));
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            she[k][hi] = A[k];
+            she[k][hi] = A[k] + P[k];
             shx[k][hi] = czero<T>();
         }
     }
@@ -923,8 +973,11 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 #pragma unroll 1
     for (int it = 0; it < a.n_mr; it++) {
         __syncthreads();
+        // sho is dead here (its readers passed the reduction's barriers): it
+        // carries the even threads' partial sums
+        pair_hops_rolled<Sh, T, G, NLC, true, true>(she, sho, 1, par, hi, l, loc, lp, locp, lbase, links, P,
+                                                    T(-0.5));   // D_oe r
         if (par == 1) {
-            dom_hops_rolled<Sh, T, G, NLC, true>(she, l, lbase, loc, links, P, T(-0.5));   // D_oe r
             clover_apply<T, G>(opaque(cs), cbase, VD, P, A);                                       // C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) sho[k][hi] = A[k];
@@ -936,8 +989,9 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
         }
         __syncthreads();
         T dots[3] = {0, 0, 0};
+        pair_hops_rolled<Sh, T, G, NLC, false, false>(sho, sho, 0, par, hi, l, loc, lp, locp, lbase, links, P,
+                                                      T(0.5));   // - D_eo C_o^-1 D_oe r
         if (par == 0) {
-            dom_hops_rolled<Sh, T, G, NLC, false>(sho, l, lbase, loc, links, P, T(0.5));   // - D_eo C_o^-1 D_oe r
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<T> rk = she[k][hi];
@@ -960,15 +1014,16 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
     __syncthreads();
 
     // ---- delta: x on even sites, C_o^-1 (rho_o - D_oe x) on odd sites
+    // x moves to the even threads' registers; shx then carries their partial sums
     if (par == 1) {
 #pragma unroll
         for (int k = 0; k < 12; k++) P[k] = ld<T, T>(rho_g, ((long)d * 12 + k) * VH + hi);
-        dom_hops_rolled<Sh, T, G, NLC, false>(shx, l, lbase, loc, links, P, T(0.5));
-        clover_apply<T, G>(opaque(cs), cbase, VD, P, A);
     } else {
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = shx[k][hi];
     }
+    pair_hops_rolled<Sh, T, G, NLC, false, false>(shx, shx, 1, par, hi, l, loc, lp, locp, lbase, links, P, T(0.5));
+    if (par == 1) clover_apply<T, G>(opaque(cs), cbase, VD, P, A);
 
     // ---- epilogue: psi += delta, stored residual, boundary terms
     {
