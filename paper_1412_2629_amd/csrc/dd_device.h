@@ -46,6 +46,31 @@ template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b)
 {
     return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
 }
+// a * b + c with one rounding
+template <typename T> __device__ __forceinline__ T fmad(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+// acc + a * b and acc + conj(a) * b as chains of fused multiply-adds (two per
+// component, where acc + (a * b) costs a multiply, a fused multiply-add and an
+// add per component: the sum cannot be fused without reassociating it)
+template <typename T> __device__ __forceinline__ cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b)
+{
+    acc.r = fmad(a.r, b.r, acc.r);
+    acc.r = fmad(-a.i, b.i, acc.r);
+    acc.i = fmad(a.r, b.i, acc.i);
+    acc.i = fmad(a.i, b.r, acc.i);
+    return acc;
+}
+template <typename T> __device__ __forceinline__ cx<T> cmacc(cx<T> acc, cx<T> a, cx<T> b)
+{
+    acc.r = fmad(a.r, b.r, acc.r);
+    acc.r = fmad(a.i, b.i, acc.r);
+    acc.i = fmad(a.r, b.i, acc.i);
+    acc.i = fmad(-a.i, b.r, acc.i);
+    return acc;
+}
 template <typename T> __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
 template <typename T> __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
 template <typename T> __device__ __forceinline__ cx<T> neg(cx<T> a) { return {-a.r, -a.i}; }
@@ -99,7 +124,8 @@ template <typename T> __device__ __forceinline__ void su3_mul(const su3<T> &U, c
     for (int s = 0; s < 2; s++)
 #pragma unroll
         for (int a = 0; a < 3; a++)
-            out[s * 3 + a] = U.m[a * 3 + 0] * h[s * 3 + 0] + U.m[a * 3 + 1] * h[s * 3 + 1] + U.m[a * 3 + 2] * h[s * 3 + 2];
+            out[s * 3 + a] = cmac(cmac(U.m[a * 3 + 0] * h[s * 3 + 0], U.m[a * 3 + 1], h[s * 3 + 1]), U.m[a * 3 + 2],
+                                  h[s * 3 + 2]);
 }
 
 // out[s][a] = sum_b conj(U[b][a]) h[s][b]
@@ -109,8 +135,8 @@ template <typename T> __device__ __forceinline__ void su3_dag_mul(const su3<T> &
     for (int s = 0; s < 2; s++)
 #pragma unroll
         for (int a = 0; a < 3; a++)
-            out[s * 3 + a] = cmulc(U.m[0 * 3 + a], h[s * 3 + 0]) + cmulc(U.m[1 * 3 + a], h[s * 3 + 1]) +
-                             cmulc(U.m[2 * 3 + a], h[s * 3 + 2]);
+            out[s * 3 + a] = cmacc(cmacc(cmulc(U.m[0 * 3 + a], h[s * 3 + 0]), U.m[1 * 3 + a], h[s * 3 + 1]),
+                                   U.m[2 * 3 + a], h[s * 3 + 2]);
 }
 
 // ---- spin projection in the chiral basis ----------------------------------
@@ -192,8 +218,8 @@ __device__ __forceinline__ void clover_block(const v2<G> *p, long base, long str
 #pragma unroll
         for (int j = 0; j < i; j++) {
             cx<T> m = ld<T, G>(p, base + (3 + tri_index(i, j)) * stride);
-            out[i] = out[i] + m * in[j];
-            out[j] = out[j] + cmulc(m, in[i]);
+            out[i] = cmac(out[i], m, in[j]);
+            out[j] = cmacc(out[j], m, in[i]);
         }
 }
 

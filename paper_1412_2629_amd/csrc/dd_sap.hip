@@ -548,17 +548,17 @@ __device__ __forceinline__ void pair_block_solve(const SapArgs &a, const int d)
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 P[k] = P[k] + scal(T(0.5), q[k]);                      // p = C_e r - D_eo C_o^-1 D_oe r
-                dots[0] += P[k].r * r[k].r + P[k].i * r[k].i;
-                dots[1] += P[k].r * r[k].i - P[k].i * r[k].r;
-                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+                dots[0] = fmad(P[k].i, r[k].i, fmad(P[k].r, r[k].r, dots[0]));
+                dots[1] = fmad(-P[k].i, r[k].r, fmad(P[k].r, r[k].i, dots[1]));
+                dots[2] = fmad(P[k].i, P[k].i, fmad(P[k].r, P[k].r, dots[2]));
             }
         }
         block_sum<VH, T, 3>(dots, red);
         const cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            shx[k][t] = shx[k][t] + alpha * r[k];
-            r[k] = r[k] - alpha * P[k];
+            shx[k][t] = cmac(shx[k][t], alpha, r[k]);
+            r[k] = cmac(r[k], neg(alpha), P[k]);
         }
     }
     __syncthreads();
@@ -626,8 +626,8 @@ __device__ __forceinline__ void clover_block_reg(const v2<G> *c, const cx<T> in[
         for (int j = 0; j < i; j++) {
             v2<G> mv = c[3 + tri_index(i, j)];
             cx<T> m = {static_cast<T>(mv.x), static_cast<T>(mv.y)};
-            out[i] = out[i] + m * in[j];
-            out[j] = out[j] + cmulc(m, in[i]);
+            out[i] = cmac(out[i], m, in[j]);
+            out[j] = cmacc(out[j], m, in[i]);
         }
 }
 
@@ -806,9 +806,9 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
             for (int k = 0; k < 12; k++) {
                 const cx<T> rk = she[k][hi];
                 P[k] = P[k] + scal(T(0.5), t[k]);
-                dots[0] += P[k].r * rk.r + P[k].i * rk.i;
-                dots[1] += P[k].r * rk.i - P[k].i * rk.r;
-                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+                dots[0] = fmad(P[k].i, rk.i, fmad(P[k].r, rk.r, dots[0]));
+                dots[1] = fmad(-P[k].i, rk.r, fmad(P[k].r, rk.i, dots[1]));
+                dots[2] = fmad(P[k].i, P[k].i, fmad(P[k].r, P[k].r, dots[2]));
             }
         }
         slot_sum<RV, NDW, T, 3>(dots, red);
@@ -817,8 +817,8 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 cx<T> rk = she[k][hi];
-                A[k] = A[k] + alpha * rk;
-                she[k][hi] = rk - alpha * P[k];
+                A[k] = cmac(A[k], alpha, rk);
+                she[k][hi] = cmac(rk, neg(alpha), P[k]);
             }
         }
     }
@@ -995,9 +995,9 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<T> rk = she[k][hi];
-                dots[0] += P[k].r * rk.r + P[k].i * rk.i;
-                dots[1] += P[k].r * rk.i - P[k].i * rk.r;
-                dots[2] += P[k].r * P[k].r + P[k].i * P[k].i;
+                dots[0] = fmad(P[k].i, rk.i, fmad(P[k].r, rk.r, dots[0]));
+                dots[1] = fmad(-P[k].i, rk.r, fmad(P[k].r, rk.i, dots[1]));
+                dots[2] = fmad(P[k].i, P[k].i, fmad(P[k].r, P[k].r, dots[2]));
             }
         }
         block_sum<VD, T, 3>(dots, red);
@@ -1006,8 +1006,8 @@ __device__ __forceinline__ void f64_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<T> rk = she[k][hi];
-                shx[k][hi] = shx[k][hi] + alpha * rk;
-                she[k][hi] = rk - alpha * P[k];
+                shx[k][hi] = cmac(shx[k][hi], alpha, rk);
+                she[k][hi] = cmac(rk, neg(alpha), P[k]);
             }
         }
     }
