@@ -644,11 +644,15 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
                 std::vector<C> wr(ns);
                 std::vector<int> todo = act;
                 for (int pass = 0; pass < 2 && !todo.empty(); pass++) {
-                    if (k > 0) {
+                    // the first pass also takes <w, w> (column k of W is w itself)
+                    const int nd = pass == 0 ? k + 1 : k;
+                    if (nd > 0) {
                         for (int i : todo)
-                            HIPCHK(sys[i].c, multidot(sys[i].sl->blas, sys[i].sl->W, nc(i), k, Wk(i, k), nc(i), s));
-                        if ((e = fetch_all(sys, st, todo, k, s))) return e;
+                            HIPCHK(sys[i].c, multidot(sys[i].sl->blas, sys[i].sl->W, nc(i), nd, Wk(i, k), nc(i), s));
+                        if ((e = fetch_all(sys, st, todo, nd, s))) return e;
                         for (int i : todo) {
+                            if (pass == 0) before[i] = st[i].h[k].x;
+                            if (k == 0) continue;
                             std::vector<C> coef(k);
                             for (int j = 0; j < k; j++) {
                                 coef[j] = C(st[i].h[j].x, st[i].h[j].y);
@@ -656,11 +660,6 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
                             }
                             if ((e = put_coef(sys[i], coef, s))) return e;
                         }
-                    }
-                    if (pass == 0) {
-                        for (int i : todo) HIPCHK(sys[i].c, norm2(sys[i].sl->blas, Wk(i, k), nc(i), s));
-                        if ((e = fetch_all(sys, st, todo, 1, s))) return e;
-                        for (int i : todo) before[i] = st[i].h[0].x;
                     }
                     for (int i : todo)
                         HIPCHK(sys[i].c, cgs_update(sys[i].sl->blas, Wk(i, k), sys[i].sl->W, nc(i), k, sys[i].sl->r,
