@@ -350,9 +350,9 @@ __device__ __forceinline__ void pair_hops_rolled(const cx<T> (*v)[Sh::VH], cx<T>
 template <class Sh> __device__ __forceinline__ long face_base(int d, int f) { return ((long)d * Sh::FTOT + Sh::foff(f)) * 6; }
 
 // rho += 1/2 phi * (the hop from the neighbouring domain across each face)
-template <class Sh, int MU, typename T, typename SS, typename G, int NLC, bool SCALED>
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC, bool SCALED, int LNLC = NLC>
 __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], int d, const int l[4], int loc,
-                                            cx<T> rho[12])
+                                            cx<T> rho[12], const v2<G> *slink = nullptr)
 {
     constexpr int VD = Sh::VD;
     const v2<SS> *face = (const v2<SS> *)a.face_in;
@@ -380,9 +380,52 @@ __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], in
 #pragma unroll
         for (int k = 0; k < 6; k++) h[k] = scal(sc, ld<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi));
         cx<T> uh[6];
-        su3<T> U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        // slink: the domain's links staged in LDS ([mu][LNLC][VD]), else global
+        su3<T> U = slink ? ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD)
+                         : ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_mul(U, h, uh);
         recon_acc<MU, -1>(rho, uh, T(wrap ? 0.5 * a.g.bc[MU] : 0.5));
+    }
+}
+
+// gather_face for all four directions at once, split in two steps so that
+// the boundary loads of every direction are in flight together: face_fetch
+// loads the site's boundary half-spinor along MU (if it has one) and its
+// weight, face_apply adds its contribution.
+template <class Sh, int MU, typename T, typename SS, bool SCALED>
+__device__ __forceinline__ void face_fetch(const SapArgs &a, const int D[4], const int l[4], cx<T> h[6], T &w,
+                                           int &side)
+{
+    const bool bwd = l[MU] == 0, fwd = l[MU] == Sh::B[MU] - 1;
+    side = bwd ? 1 : fwd ? 2 : 0;
+    if (!(bwd || fwd)) return;
+    const v2<SS> *face = (const v2<SS> *)a.face_in;
+    int Dn[4] = {D[0], D[1], D[2], D[3]};
+    const bool wrap = bwd ? D[MU] == 0 : D[MU] == a.g.n[MU] - 1;
+    Dn[MU] = bwd ? (wrap ? a.g.n[MU] - 1 : D[MU] - 1) : (wrap ? 0 : D[MU] + 1);
+    const int dn = Dn[0] + a.g.n[0] * (Dn[1] + a.g.n[1] * (Dn[2] + a.g.n[2] * Dn[3]));
+    // backward hop: the -mu neighbour's +mu face; forward: the +mu neighbour's -mu face
+    const long fb = face_base<Sh>(dn, 2 * MU + (bwd ? 1 : 0));
+    const int fi = Sh::template face_index<MU>(l);
+#pragma unroll
+    for (int k = 0; k < 6; k++) h[k] = ld<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi);
+    const T sc = SCALED ? T(a.face_in_scale[dn]) : T(1);
+    w = sc * T(wrap ? 0.5 * a.g.bc[MU] : 0.5);
+}
+
+template <class Sh, int MU, typename T, typename G, int NLC, int LNLC>
+__device__ __forceinline__ void face_apply(const SapArgs &a, int d, int loc, const v2<G> *slink, const cx<T> h[6],
+                                           T w, int side, cx<T> rho[12])
+{
+    constexpr int VD = Sh::VD;
+    if (side == 1) {
+        recon_acc<MU, +1>(rho, h, w);
+    } else if (side == 2) {
+        cx<T> uh[6];
+        su3<T> U = slink ? ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD)
+                         : ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        su3_mul(U, h, uh);
+        recon_acc<MU, -1>(rho, uh, w);
     }
 }
 
@@ -696,20 +739,19 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     const v2<G> *cs = (const v2<G> *)a.cs;
     const long sbase = (long)d * 12 * VD + loc;
 
-    // ---- stage the links into LDS, the site's clover block into registers
+    // ---- stage the links into LDS, the site's clover block into registers.
+    // Every global load is issued before the first LDS store: the loads go
+    // through generic pointers, so a load placed after an LDS store must wait
+    // for it, and with loads and stores interleaved each load would wait for
+    // the previous one's data.
     const v2<G> *links = slink;
     long lbase = 0;
-    if (!live) {
-    } else if constexpr (LINK_LDS && LNLC == NLC) {
-        const long lb = (long)d * 4 * NLC * VD + loc;
+    v2<G> lt[LINK_LDS ? 4 * NLC : 1];
+    if constexpr (LINK_LDS) {
+        if (live) {
+            const long lb = (long)d * 4 * NLC * VD + loc;
 #pragma unroll
-        for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = glinks[lb + (long)q * VD];
-    } else if constexpr (LINK_LDS) {
-#pragma unroll
-        for (int mu = 0; mu < 4; mu++) {
-            const su3<T> U = ld_link<T, G, NLC>(glinks, (long)d * 4 * NLC * VD + (long)mu * NLC * VD + loc, VD);
-#pragma unroll
-            for (int e = 0; e < 9; e++) st<T, G>(slink, (long)(mu * 9 + e) * VD + loc, U.m[e]);
+            for (int q = 0; q < 4 * NLC; q++) lt[q] = glinks[lb + (long)q * VD];
         }
     } else {
         links = glinks;
@@ -720,6 +762,18 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
     if constexpr (CL_REG) {
 #pragma unroll
         for (int q = 0; q < 36; q++) cl[q] = live ? cs[cbase + (long)q * VD] : v2<G>{};
+    }
+    if (!live) {
+    } else if constexpr (LINK_LDS && LNLC == NLC) {
+#pragma unroll
+        for (int q = 0; q < 4 * NLC; q++) slink[q * VD + loc] = lt[q];
+    } else if constexpr (LINK_LDS) {
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            const su3<T> U = ld_link<T, G, NLC>(lt + mu * NLC, 0, 1);
+#pragma unroll
+            for (int e = 0; e < 9; e++) st<T, G>(slink, (long)(mu * 9 + e) * VD + loc, U.m[e]);
+        }
     }
     // this site's clover block (C_e on even sites, C_o^-1 on odd sites) times in
     auto clover = [&](const cx<T> in[12], cx<T> out[12]) {
@@ -745,10 +799,18 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         for (int k = 0; k < 12; k++) A[k] = czero<T>();
     }
     if (f.faces_in && live) {
-        gather_face<Sh, 0, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
-        gather_face<Sh, 1, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
-        gather_face<Sh, 2, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
-        gather_face<Sh, 3, T, SS, G, NLC, SCALED>(a, D, d, l, loc, A);
+        cx<T> hf[4][6];
+        T wf[4] = {0, 0, 0, 0};
+        int sf[4];
+        face_fetch<Sh, 0, T, SS, SCALED>(a, D, l, hf[0], wf[0], sf[0]);
+        face_fetch<Sh, 1, T, SS, SCALED>(a, D, l, hf[1], wf[1], sf[1]);
+        face_fetch<Sh, 2, T, SS, SCALED>(a, D, l, hf[2], wf[2], sf[2]);
+        face_fetch<Sh, 3, T, SS, SCALED>(a, D, l, hf[3], wf[3], sf[3]);
+        const v2<G> *sl = LINK_LDS ? slink : nullptr;
+        face_apply<Sh, 0, T, G, NLC, LNLC>(a, d, loc, sl, hf[0], wf[0], sf[0], A);
+        face_apply<Sh, 1, T, G, NLC, LNLC>(a, d, loc, sl, hf[1], wf[1], sf[1], A);
+        face_apply<Sh, 2, T, G, NLC, LNLC>(a, d, loc, sl, hf[2], wf[2], sf[2], A);
+        face_apply<Sh, 3, T, G, NLC, LNLC>(a, d, loc, sl, hf[3], wf[3], sf[3], A);
     }
 
     // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0
