@@ -350,9 +350,9 @@ __device__ __forceinline__ void pair_hops_rolled(const cx<T> (*v)[Sh::VH], cx<T>
 template <class Sh> __device__ __forceinline__ long face_base(int d, int f) { return ((long)d * Sh::FTOT + Sh::foff(f)) * 6; }
 
 // rho += 1/2 phi * (the hop from the neighbouring domain across each face)
-template <class Sh, int MU, typename T, typename SS, typename G, int NLC, bool SCALED, int LNLC = NLC>
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC, bool SCALED>
 __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], int d, const int l[4], int loc,
-                                            cx<T> rho[12], const v2<G> *slink = nullptr)
+                                            cx<T> rho[12])
 {
     constexpr int VD = Sh::VD;
     const v2<SS> *face = (const v2<SS> *)a.face_in;
@@ -380,9 +380,7 @@ __device__ __forceinline__ void gather_face(const SapArgs &a, const int D[4], in
 #pragma unroll
         for (int k = 0; k < 6; k++) h[k] = scal(sc, ld<T, SS>(face, fb + (long)k * Sh::FS[MU] + fi));
         cx<T> uh[6];
-        // slink: the domain's links staged in LDS ([mu][LNLC][VD]), else global
-        su3<T> U = slink ? ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD)
-                         : ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        su3<T> U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_mul(U, h, uh);
         recon_acc<MU, -1>(rho, uh, T(wrap ? 0.5 * a.g.bc[MU] : 0.5));
     }
@@ -413,7 +411,7 @@ __device__ __forceinline__ void face_fetch(const SapArgs &a, const int D[4], con
     w = sc * T(wrap ? 0.5 * a.g.bc[MU] : 0.5);
 }
 
-template <class Sh, int MU, typename T, typename G, int NLC, int LNLC>
+template <class Sh, int MU, typename T, typename G, int NLC, int LNLC, bool FROM_LDS>
 __device__ __forceinline__ void face_apply(const SapArgs &a, int d, int loc, const v2<G> *slink, const cx<T> h[6],
                                            T w, int side, cx<T> rho[12])
 {
@@ -422,16 +420,17 @@ __device__ __forceinline__ void face_apply(const SapArgs &a, int d, int loc, con
         recon_acc<MU, +1>(rho, h, w);
     } else if (side == 2) {
         cx<T> uh[6];
-        su3<T> U = slink ? ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD)
-                         : ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        su3<T> U;
+        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD);
+        else U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_mul(U, h, uh);
         recon_acc<MU, -1>(rho, uh, w);
     }
 }
 
-template <class Sh, int MU, typename T, typename SS, typename G, int NLC>
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC, int LNLC = NLC, bool FROM_LDS = false>
 __device__ __forceinline__ void write_face(const SapArgs &a, int d, const int l[4], int loc, const cx<T> delta[12],
-                                           T inv_sc)
+                                           T inv_sc, const v2<G> *slink = nullptr)
 {
     constexpr int VD = Sh::VD;
     v2<SS> *face = (v2<SS> *)a.face;
@@ -445,7 +444,10 @@ __device__ __forceinline__ void write_face(const SapArgs &a, int d, const int l[
     } else if (l[MU] == Sh::B[MU] - 1) {
         cx<T> uh[6];
         proj<MU, +1>(delta, h);
-        su3<T> U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
+        // FROM_LDS: the domain's links staged in slink ([mu][LNLC][VD]), else global
+        su3<T> U;
+        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD);
+        else U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_dag_mul(U, h, uh);
         long fb = face_base<Sh>(d, 2 * MU + 1);
         int fi = Sh::template face_index<MU>(l);
@@ -806,11 +808,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         face_fetch<Sh, 1, T, SS, SCALED>(a, D, l, hf[1], wf[1], sf[1]);
         face_fetch<Sh, 2, T, SS, SCALED>(a, D, l, hf[2], wf[2], sf[2]);
         face_fetch<Sh, 3, T, SS, SCALED>(a, D, l, hf[3], wf[3], sf[3]);
-        const v2<G> *sl = LINK_LDS ? slink : nullptr;
-        face_apply<Sh, 0, T, G, NLC, LNLC>(a, d, loc, sl, hf[0], wf[0], sf[0], A);
-        face_apply<Sh, 1, T, G, NLC, LNLC>(a, d, loc, sl, hf[1], wf[1], sf[1], A);
-        face_apply<Sh, 2, T, G, NLC, LNLC>(a, d, loc, sl, hf[2], wf[2], sf[2], A);
-        face_apply<Sh, 3, T, G, NLC, LNLC>(a, d, loc, sl, hf[3], wf[3], sf[3], A);
+        face_apply<Sh, 0, T, G, NLC, LNLC, LINK_LDS>(a, d, loc, slink, hf[0], wf[0], sf[0], A);
+        face_apply<Sh, 1, T, G, NLC, LNLC, LINK_LDS>(a, d, loc, slink, hf[1], wf[1], sf[1], A);
+        face_apply<Sh, 2, T, G, NLC, LNLC, LINK_LDS>(a, d, loc, slink, hf[2], wf[2], sf[2], A);
+        face_apply<Sh, 3, T, G, NLC, LNLC, LINK_LDS>(a, d, loc, slink, hf[3], wf[3], sf[3], A);
     }
 
     // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0
@@ -936,10 +937,10 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
         }
         T inv = T(1) / sc;
         if (live) {
-            write_face<Sh, 0, T, SS, G, NLC>(a, d, l, loc, A, inv);
-            write_face<Sh, 1, T, SS, G, NLC>(a, d, l, loc, A, inv);
-            write_face<Sh, 2, T, SS, G, NLC>(a, d, l, loc, A, inv);
-            write_face<Sh, 3, T, SS, G, NLC>(a, d, l, loc, A, inv);
+            write_face<Sh, 0, T, SS, G, NLC, LNLC, LINK_LDS>(a, d, l, loc, A, inv, slink);
+            write_face<Sh, 1, T, SS, G, NLC, LNLC, LINK_LDS>(a, d, l, loc, A, inv, slink);
+            write_face<Sh, 2, T, SS, G, NLC, LNLC, LINK_LDS>(a, d, l, loc, A, inv, slink);
+            write_face<Sh, 3, T, SS, G, NLC, LNLC, LINK_LDS>(a, d, l, loc, A, inv, slink);
         }
     }
 }
