@@ -132,7 +132,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the lattice is solved whole on a single "
-              "MI355X; multi-GPU sharding is not part of this build", file=sys.stderr)
+              "MI355X; the library does not shard a lattice across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch
