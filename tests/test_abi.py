@@ -137,3 +137,15 @@ def test_tune_domain_host_paths():
 def test_status_strings():
     assert ddqcd.status_string(ddqcd.ERR_NOT_CONVERGED) == "DDQCD_ERR_NOT_CONVERGED"
     assert ddqcd.status_string(99) == "unknown status"
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits with status 2 and says why, before any GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""
