@@ -32,8 +32,8 @@ CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 # they were taken on, identified by a hash; after any change to those sources
 # the figure is reported as null until it is measured again.
 KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
-MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 62.25e6, "sources": "26b2de77fa13a052"},
-                    "C3": {"bytes_per_launch": 599.83e6, "sources": "26b2de77fa13a052"}}
+MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 62.26e6, "sources": "6143a89311d60dc3"},
+                    "C3": {"bytes_per_launch": 599.84e6, "sources": "6143a89311d60dc3"}}
 
 
 def log(*a):

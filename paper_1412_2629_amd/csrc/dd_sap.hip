@@ -67,13 +67,34 @@ template <int BX, int BY, int BZ, int BT> struct Shape {
 
 // ---- block reductions over all VD threads (deterministic order) -----------
 
+// Sum over the 64 lanes of a wave, returned to every lane (all lanes active):
+// DPP permutes within each 16-lane row (lane ^ 1, lane ^ 2, then the mirrored
+// halves of 8 and of 16 lanes) leave every lane with its row's sum; the four
+// row sums are read out and added.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 template <int VD, typename T, int N> __device__ __forceinline__ void block_sum(T (&v)[N], T *red)
 {
     if constexpr (VD >= 64) {
         constexpr int NW = VD / 64;
 #pragma unroll
-        for (int q = 0; q < N; q++)
-            for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        for (int q = 0; q < N; q++) v[q] = wave_sum(v[q]);
         int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0)
 #pragma unroll
