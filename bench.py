@@ -1,16 +1,22 @@
 #!/usr/bin/env python
 """Time-to-solution of the SAP-preconditioned FGCR Wilson-clover solve on one GPU.
 
-One step = one full solve A x = b to true relative residual 1e-10 (all rows
-of the hot path: FP64 operator, Schwarz preconditioner with MR block solves,
-Gram-Schmidt, solution update), inputs resident in HBM, gauge field and
-clover term loaded beforehand.  Prints one JSON line.
+One step = one full solve A x = b to true relative residual 1e-10 of every
+right-hand side of the workload (all rows of the hot path: FP64 operator,
+Schwarz preconditioner with MR block solves, Gram-Schmidt, solution update),
+inputs resident in HBM, gauge field and clover term loaded beforehand.
+Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload C2|C3|C4|C5|C1]
+  python bench.py [--steps K] [--warmup W] [--workload C4|C3|C2|C5|C1]
 
-C2 (16^3x32, FP32 block solves) is the default.  C4 solves 12 point sources
-on the 32^3x64 lattice together, C5 the 24-lattice uneven batch in one
-ddqcd_solve_batch call; for them one step is the whole batch.
+C4 is the default: 12 point sources on the 32^3x64 lattice solved together
+(FP16-storage block solves, FP64 FGCR per right-hand side), the largest
+single-GPU workload.  C3 is one Gaussian source on that lattice, C2 the
+16^3x32 lattice with FP32 block solves, C5 the 24-lattice uneven batch in one
+ddqcd_solve_batch call; for the batched workloads one step is the whole batch.
+Beside the timed solve the same workload is solved with the FP64
+preconditioner (the plain path) and with FP64 BiCGstab (no domain
+decomposition), and the oracle is timed on the host.
 """
 import argparse
 import json
@@ -117,7 +123,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C4", choices=["C1", "C2", "C3", "C4", "C5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="sweeps", choices=["sweeps", "graph"],
                     help="block-solve launches issued one by one, or replayed from a captured HIP graph")
@@ -199,41 +205,16 @@ def main():
 
     traffic = None
     m = MEASURED_TRAFFIC.get(args.workload)
-    if m and m["sources"] == kernel_sources_hash():
+    if m and m["sources"] == kernel_sources_hash() and args.schwarz == "multiplicative":
         traffic = m["bytes_per_launch"]
 
-    fp64 = None
     w0 = systems[0].w
-    if not args.no_fp64 and len(systems) == 1 and len(systems[0].srcs) == 1 and w0.prec != "f64":
-        log("[bench] FP64-preconditioner comparison solve")
-        s = systems[0]
-        s.ctx.set_sap(w0.n_cycles, w0.n_mr, "f64")
-        solve_all(systems, ddqcd)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x64, i64 = solve_all(systems, ddqcd)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
-        s.ctx.set_sap(w0.n_cycles, w0.n_mr, w0.prec)
-        diff = float(torch.linalg.vector_norm(xs[0] - x64[0]) / torch.linalg.vector_norm(x64[0]))
-        fp64 = {"fp64_sap_solve_s": round(t64, 5), "fp64_sap_fgcr_steps": i64[0]["iters"],
-                "mixed_solve_s": round(t_solve, 6), "mixed_fgcr_steps": iters[0],
-                "speedup_mixed_over_fp64": round(t64 / t_solve, 3),
-                "rel_diff_mixed_vs_fp64_solution": diff}
-
-    # the solver without domain decomposition (FP64 BiCGstab) on the same GPU
+    fp64 = None
+    if not args.no_fp64 and w0.prec != "f64":
+        fp64 = fp64_comparison(systems, xs, iters, t_solve, ddqcd)
     nodd = None
-    if not args.no_fp64 and len(systems) == 1 and len(systems[0].srcs) == 1:
-        log("[bench] non-DD comparison solve (FP64 BiCGstab)")
-        s = systems[0]
-        s.ctx.solve_bicgstab(s.b)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        xb, ib, stb = s.ctx.solve_bicgstab(s.b)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t1
-        nodd = {"bicgstab_fp64_solve_s": round(tb, 5), "bicgstab_iters": ib["iters"],
-                "converged": bool(ib["converged"]), "speedup_dd_over_non_dd": round(tb / t_solve, 3)}
+    if not args.no_fp64:
+        nodd = non_dd_comparison(systems, t_solve)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -272,19 +253,117 @@ def main():
         "true_rel_residual": true_res,
         "time_split_ms": {k: round(sum(inf[0][k] for _, inf in runs) / len(runs), 3)
                           for k in ("t_sap_ms", "t_A_ms", "t_gs_ms", "t_other_ms")},
+        "fgcr_gram_schmidt": gram_schmidt_rate(systems, iters, runs),
         "sap_dslash_gflops": round(dslash_gflops, 1),
         "sap_total_tflops": round(achieved_tflops, 3),
         "sap_launches_per_step": int(launches),
         "sap_launch_ms": round(launch_ms, 5),
         "setup_s": round(t_tune, 3),
-        "roofline": {"kernel": "k_sap_lds", "bound": "alu", "achieved": round(achieved_tflops, 3),
-                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_PEAK_TFLOPS, 4),
-                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)"},
+        "roofline": roofline(systems, achieved_tflops, launch_ms, traffic),
         "mixed_vs_fp64": fp64,
         "dd_vs_non_dd": nodd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def gram_schmidt_rate(systems, iters, runs):
+    """Algorithmic HBM rate of FGCR's orthogonalisation (FP64 vectors, 192 B
+    per site): at step k of a cycle the multi-dot reads k + 2 vectors, the
+    update reads k + 2 and writes one, the normalisation reads and writes two;
+    divided by the Gram-Schmidt time the library measures on the stream."""
+    byts = 0.0
+    rhs = [s for s in systems for _ in s.srcs]
+    for s, n in zip(rhs, iters):
+        m = s.w.restart
+        vec = s.w.volume * 192
+        for step in range(n):
+            k = step % m
+            byts += (2 * k + 9) * vec
+    t_gs = sum(inf[0]["t_gs_ms"] for _, inf in runs) / len(runs)
+    return {"algorithmic_GB": round(byts / 1e9, 3), "t_ms": round(t_gs, 3),
+            "GB_per_s": round(byts / (t_gs * 1e-3) / 1e9, 1) if t_gs > 0 else None}
+
+
+def roofline(systems, achieved_tflops, launch_ms, traffic):
+    """The block-solve kernel against both roofs: algorithmic flops per launch
+    against FP32 vector peak, algorithmic bytes per launch (geometry's byte
+    model: links and clover once per domain, spinor data per right-hand side)
+    against HBM peak.  The bound is the roof the kernel is closer to."""
+    from paper_1412_2629_amd import geometry
+    w0 = systems[0].w
+    bytes_launch = 0.0
+    for s in systems:
+        w = s.w
+        nd = w.volume // geometry.volume(w.domain)
+        per = geometry.sap_bytes_per_domain(w.domain, w.prec if w.prec != "f64" else "f32", len(s.srcs))
+        bytes_launch += nd / 2 * per
+    gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
+    alu_frac = achieved_tflops / FP32_PEAK_TFLOPS
+    hbm_frac = gbs / HBM_PEAK_GBS
+    kernel = "k_sap_lds" if w0.prec != "f64" else "k_sap_f64"
+    common = {"kernel": kernel, "traffic": traffic,
+              "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)",
+              "algorithmic_bytes_per_launch": round(bytes_launch), "launch_ms": round(launch_ms, 5),
+              "alu_frac": round(alu_frac, 4), "hbm_frac": round(hbm_frac, 4)}
+    if alu_frac >= hbm_frac:
+        return {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4), **common}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_frac, 4), **common}
+
+
+def fp64_comparison(systems, xs, iters, t_solve, ddqcd):
+    """The same workload with the FP64 preconditioner on the same domains (the
+    plain FP64 SAP + FGCR path): time, steps and the distance between the two
+    solutions.  Lattices whose domain shape has no FP64 block-solve kernel keep
+    their low-precision preconditioner and are listed."""
+    import torch
+    log("[bench] FP64-preconditioner comparison solve")
+    kept = []
+    for s in systems:
+        w = s.w
+        try:
+            s.ctx.set_sap(w.n_cycles, w.n_mr, "f64")
+        except ddqcd.DDQCDError:
+            kept.append(f"{w.lattice} {w.domain}")
+    solve_all(systems, ddqcd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x64, i64 = solve_all(systems, ddqcd)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t1
+    for s in systems:
+        s.ctx.set_sap(s.w.n_cycles, s.w.n_mr, s.w.prec)
+    diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xs, x64))
+    steps64 = [i["iters"] for i in i64]
+    return {"fp64_sap_solve_s": round(t64, 5), "fp64_sap_fgcr_steps": steps64 if len(steps64) > 1 else steps64[0],
+            "mixed_solve_s": round(t_solve, 6), "mixed_fgcr_steps": iters if len(iters) > 1 else iters[0],
+            "speedup_mixed_over_fp64": round(t64 / t_solve, 3),
+            "rel_diff_mixed_vs_fp64_solution": diff, "lattices_without_fp64_kernel": kept}
+
+
+def non_dd_comparison(systems, t_solve):
+    """FP64 BiCGstab without preconditioner (the paper's non-DD solver) on the
+    same GPU, one right-hand side after the other, after one untimed warm-up
+    solve of the first."""
+    import torch
+    log("[bench] non-DD comparison solves (FP64 BiCGstab)")
+    s0 = systems[0]
+    s0.ctx.solve_bicgstab(s0.b if len(s0.srcs) == 1 else s0.b[0].contiguous())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    its, ok = [], True
+    for s in systems:
+        for k in range(len(s.srcs)):
+            b = s.b if len(s.srcs) == 1 else s.b[k].contiguous()
+            _, ib, _ = s.ctx.solve_bicgstab(b)
+            its.append(ib["iters"])
+            ok = ok and bool(ib["converged"])
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t1
+    return {"bicgstab_fp64_solve_s": round(tb, 5), "bicgstab_iters": its if len(its) > 1 else its[0],
+            "converged": ok, "speedup_dd_over_non_dd": round(tb / t_solve, 3)}
 
 
 def cpu_baseline(systems, gpu_iters):

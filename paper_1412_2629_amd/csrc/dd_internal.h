@@ -65,19 +65,6 @@ struct SapArgs {
     void *rho_tmp;      // odd-site right-hand sides [d][12][Vd/2] when not kept in LDS
     int active;         // 0: skip this system (already converged)
 };
-// The persistent form: every block solve of one preconditioner call in one
-// launch, dequeued from a work queue and ordered by per-domain epoch counters.
-struct QueueArgs {
-    int *epoch;         // [nd] visits completed by each domain (monotone across calls)
-    int *counter;       // task counter (reset by the launch)
-    int *error;         // set when a dependency wait exceeds the spin limit
-    int base;           // common epoch of all domains when the call starts
-    int n_cycles;
-    int nd, nblack;
-    const int *order;   // [nd] black domains, then white domains
-};
-hipError_t sap_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s);
-hipError_t queue_reset_epochs(int *epoch, int nd, int *error, hipStream_t s);
 bool sap_shape_supported(const int b[4]);
 bool sap_prec_supported(const int b[4], int prec);
 long sap_face_sites(const int b[4]);

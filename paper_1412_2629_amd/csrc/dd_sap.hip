@@ -19,6 +19,9 @@
 // address and no atomics are needed.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "dd_device.h"
 #include "dd_internal.h"
 
@@ -1206,102 +1209,34 @@ __global__ __launch_bounds__(Sh::VH) void k_sap_sweep(const SapArgs *args, const
     pair_block_solve<Sh, T, SS, PS, G, NLC, SCALED, RHO_LDS>(a, it.y);
 }
 
-// ---- persistent work-queue kernel -------------------------------------------
-//
-// All block solves of one preconditioner call in one launch.  Tasks are the
-// pairs (cycle s, domain d), dequeued in the order: cycle 0 black domains,
-// cycle 0 white domains, cycle 1 black, ...  A task may start when the
-// neighbouring domains have finished the visit it depends on (black at cycle
-// s: the white neighbours' cycle s-1; white at cycle s: the black neighbours'
-// cycle s), read from per-domain epoch counters.  Every task waited on has a
-// smaller queue index, so it has already been dequeued by a running
-// workgroup: the queue drains without any assumption on how many workgroups
-// are resident, and white domains of cycle s overlap black domains of cycle
-// s+1 wherever their neighbours are done.  A wait that exceeds a spin limit
-// raises the error flag, and every later wait then gives up at once, so the
-// grid always drains.
-
-// Polling uses relaxed system-scope loads: they read memory past the L2 of
-// this XCD without invalidating it.  (Acquire loads would invalidate the L2
-// on every poll; with most workgroups polling, that continuous invalidation
-// starves the workgroups whose results are being waited for.)  One acquire
-// fence follows a successful wait; the counter, the epochs and the error flag
-// are system-scope atomics, so they are coherent across the XCDs' L2 caches.
-constexpr int QUEUE_SPIN_LIMIT = 1 << 19;
-
-__device__ __forceinline__ bool wait_epoch(const QueueArgs &q, int nb, int need)
-{
-    int spins = 0;
-    while (__hip_atomic_load(&q.epoch[nb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
-        if (__hip_atomic_load(q.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) return false;
-        if (++spins > QUEUE_SPIN_LIMIT) {
-            __hip_atomic_fetch_or(q.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(32);
-    }
-    return true;
-}
-
-__device__ __forceinline__ bool wait_neighbours(const QueueArgs &q, const Geo &g, int d, int need)
-{
-    int D[4];
-    {
-        int r = d;
-        D[0] = r % g.n[0]; r /= g.n[0];
-        D[1] = r % g.n[1]; r /= g.n[1];
-        D[2] = r % g.n[2];
-        D[3] = r / g.n[2];
-    }
-    for (int mu = 0; mu < 4; mu++)
-        for (int step = -1; step <= 1; step += 2) {
-            int E[4] = {D[0], D[1], D[2], D[3]};
-            E[mu] = (E[mu] + step + g.n[mu]) % g.n[mu];
-            int nb = E[0] + g.n[0] * (E[1] + g.n[1] * (E[2] + g.n[2] * E[3]));
-            if (!wait_epoch(q, nb, need)) return false;
-        }
-    return true;
-}
-
-template <class Sh, typename SS, typename G, bool SCALED>
-__global__ __launch_bounds__(Sh::VD) void k_sap_queue(SapArgs a, QueueArgs q)
-{
-    a.face_in = a.face;
-    a.face_in_scale = a.face_scale;
-    __shared__ int task_s, ok_s;
-    const int ntask = q.n_cycles * q.nd;
-    for (;;) {
-        if (threadIdx.x == 0) task_s = __hip_atomic_fetch_add(q.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __syncthreads();
-        // the task is the same for the whole workgroup: keep it in scalar registers
-        const int t = __builtin_amdgcn_readfirstlane(task_s);
-        __syncthreads();
-        if (t >= ntask) break;
-        const int s = t / q.nd, k = t - s * q.nd;
-        const int d = __builtin_amdgcn_readfirstlane(q.order[k]);
-        const int colour = k >= q.nblack;
-        if (threadIdx.x == 0) ok_s = wait_neighbours(q, a.g, d, q.base + s + colour);
-        __syncthreads();
-        if (!__builtin_amdgcn_readfirstlane(ok_s)) continue;
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);   // system scope: see the neighbours' results
-        const int last = s == q.n_cycles - 1;
-        lds_block_solve<Sh, 1, float, SS, float, G, 6, 6, SCALED, true, true>(a, d, Visit{s == 0, !(s == 0 && colour == 0), last, !(last && colour == 1), !last});
-        __threadfence_system();                     // this block's results reach memory ...
-        __syncthreads();
-        if (threadIdx.x == 0)                       // ... before its epoch moves on
-            __hip_atomic_store(&q.epoch[d], q.base + s + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
-__global__ void k_queue_reset(int *counter) { *counter = 0; }
-
-__global__ void k_epoch_reset(int *epoch, int nd, int *error)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x) epoch[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *error = 0;
-}
-
 // ---- dispatch ---------------------------------------------------------------
+
+// Every block-solve launch goes through here: the workgroup size must not
+// exceed the kernel's launch bound (the register allocation is made for that
+// bound), which is read from the code object once per kernel and checked on
+// the host before the launch.
+template <typename... P, typename... A>
+static hipError_t launch_bounded(void (*kernel)(P...), unsigned grid, unsigned block, hipStream_t s, A... args)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> bound;
+    const void *key = reinterpret_cast<const void *>(kernel);
+    int maxt;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = bound.find(key);
+        if (it == bound.end()) {
+            hipFuncAttributes at;
+            const hipError_t e = hipFuncGetAttributes(&at, key);
+            if (e != hipSuccess) return e;
+            it = bound.emplace(key, at.maxThreadsPerBlock).first;
+        }
+        maxt = it->second;
+    }
+    if (block == 0 || (int)block > maxt) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, args...);
+    return hipGetLastError();
+}
 
 template <class Sh>
 static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
@@ -1310,10 +1245,10 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
         // FP64: one thread per even/odd site pair on 2^4 domains, else the LDS
         // layout (whole waves only: no FP64 kernel for padded workgroups)
         if constexpr (Sh::VD == 16)
-            hipLaunchKernelGGL((k_sap_sweep<Sh, double, double, double, double, 9, false, false>), dim3(nitems),
-                               dim3(Sh::VH), 0, s, args, items, v);
+            return launch_bounded(k_sap_sweep<Sh, double, double, double, double, 9, false, false>, nitems, Sh::VH, s,
+                                  args, items, v);
         else if constexpr (Sh::VD % 64 == 0)
-            hipLaunchKernelGGL((k_sap_f64<Sh>), dim3(nitems), dim3(Sh::VD), 0, s, args, items, v);
+            return launch_bounded(k_sap_f64<Sh>, nitems, Sh::VD, s, args, items, v);
         else
             return hipErrorInvalidValue;
     } else {
@@ -1321,13 +1256,12 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
         constexpr int NT = NDW > 1 ? Sh::VD * NDW : Sh::NT;
         if (nitems % NDW) return hipErrorInvalidValue;
         if (prec == P32)
-            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, float, float, float, 6, 6, false, true, true>),
-                               dim3(nitems / NDW), dim3(NT), 0, s, args, items, v);
+            return launch_bounded(k_sap_lds<Sh, NDW, float, float, float, float, 6, 6, false, true, true>, nitems / NDW,
+                                  NT, s, args, items, v);
         else
-            hipLaunchKernelGGL((k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, 9, true, true, true>),
-                               dim3(nitems / NDW), dim3(NT), 0, s, args, items, v);
+            return launch_bounded(k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, 9, true, true, true>,
+                                  nitems / NDW, NT, s, args, items, v);
     }
-    return hipGetLastError();
 }
 
 int sap_domains_per_workgroup(int shape, int prec) { return shape == 0 && prec != P64 ? 8 : 1; }
@@ -1365,39 +1299,6 @@ long sap_face_sites(const int b[4])
 {
     long Vd = (long)b[0] * b[1] * b[2] * b[3];
     return 2 * (Vd / b[0] + Vd / b[1] + Vd / b[2] + Vd / b[3]);
-}
-
-template <class Sh> static hipError_t launch_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_queue_reset, 1, 1, 0, s, q.counter);
-    int per_cu = 0;
-    hipError_t e;
-    if (prec == P32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sap_queue<Sh, float, float, false>, Sh::VD, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sap_queue<Sh, half_t, half_t, true>, Sh::VD, 0);
-    if (e != hipSuccess) return e;
-    long grid = (long)n_cu * (per_cu > 0 ? per_cu : 1);
-    long ntask = (long)q.n_cycles * q.nd;
-    if (grid > ntask) grid = ntask;
-    if (prec == P32) hipLaunchKernelGGL((k_sap_queue<Sh, float, float, false>), dim3(grid), dim3(Sh::VD), 0, s, a, q);
-    else hipLaunchKernelGGL((k_sap_queue<Sh, half_t, half_t, true>), dim3(grid), dim3(Sh::VD), 0, s, a, q);
-    return hipGetLastError();
-}
-
-hipError_t sap_queue(const SapArgs &a, const QueueArgs &q, int prec, int n_cu, hipStream_t s)
-{
-    if (prec == P64 || !sap_prec_supported(a.g.b, prec)) return hipErrorInvalidValue;
-    switch (sap_shape_id(a.g.b)) {
-        case 0: return launch_queue<Shape<2, 2, 2, 2>>(a, q, prec, n_cu, s);
-        case 1: return launch_queue<Shape<4, 4, 4, 4>>(a, q, prec, n_cu, s);
-        case 2: return launch_queue<Shape<8, 4, 4, 4>>(a, q, prec, n_cu, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t queue_reset_epochs(int *epoch, int nd, int *error, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_epoch_reset, 64, 256, 0, s, epoch, nd, error);
-    return hipGetLastError();
 }
 
 hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,

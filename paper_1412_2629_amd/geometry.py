@@ -117,3 +117,25 @@ def a_bytes_per_site(prec):
     if prec == "f16":
         return 48 + 4 * 12 * 2 + 72 * 2 + 48
     raise ValueError(prec)
+
+
+def face_sites(b):
+    """Sites on the faces of a domain, counted once per face (a site on two
+    faces counts twice): the boundary half-spinors one domain writes."""
+    Vd = volume(b)
+    return sum(2 * (Vd // b[m]) for m in range(4))
+
+
+def sap_bytes_per_domain(b, prec, nrhs=1):
+    """Algorithmic HBM bytes of one visit of one domain by nrhs right-hand
+    sides in a SAP half-sweep (each field read once, each result written once):
+    the two-row links and the site clover blocks (C_e / C_o^-1) once, and per
+    right-hand side the stored block residual of the even sites (read and
+    written), the solution accumulator (FP32, read and written) and the
+    boundary half-spinors (read from the neighbours, written for them).  prec:
+    "f32" or "f16" storage of links, clover, residual and boundary terms."""
+    Vd = volume(b)
+    c = {"f32": 8, "f16": 4}[prec]          # bytes per stored complex number
+    shared = Vd * (4 * 6 * c + 36 * c)
+    per_rhs = Vd // 2 * 12 * c * 2 + Vd * 12 * 8 * 2 + face_sites(b) * 6 * c * 2
+    return shared + nrhs * per_rhs

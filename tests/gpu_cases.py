@@ -14,6 +14,28 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def site_err(got, want):
+    """(normwise relative error, largest error of one site relative to the
+    RMS site norm of want): an error confined to a few sites (a face layer, one
+    domain) shows in the second figure even where the norm hides it."""
+    g = np.asarray(got).reshape(-1, 12)
+    w = np.asarray(want).reshape(-1, 12)
+    d = np.linalg.norm(g - w, axis=1)
+    n = np.linalg.norm(w, axis=1)
+    return float(np.linalg.norm(d) / np.linalg.norm(n)), float(d.max() / np.sqrt(np.mean(n * n)))
+
+
+# Block-solve output against the FP64 oracle (derivation in the design notes):
+# FP32 arithmetic accumulates a few unit roundoffs per MR step; FP16 storage
+# rounds each stored link, clover entry, block residual and boundary term once
+# per half-sweep.  Each Schwarz cycle contracts the error the earlier cycles
+# left, so the error does not grow with the cycle count.  Normwise bounds:
+# 8 u (FP32, u = 2^-24) and 4 u (FP16, u = 2^-11); one site's error may reach
+# SITE_FACTOR times that relative to the RMS site norm.
+SAP_TOL = {"f64": 1e-12, "f32": 8 * 2.0 ** -24, "f16": 4 * 2.0 ** -11}
+SITE_FACTOR = 4.0
+
+
 def dev(a):
     import torch
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
@@ -67,6 +89,17 @@ SMALL = [
     Case("16x8x8x8/8x4^3", (16, 8, 8, 8), (8, 4, 4, 4), 0.1355, 1.5, 0.5, 131, 4, 5),
     Case("8x8x8x16/4^3x8", (8, 8, 8, 16), (4, 4, 4, 8), 0.13, 1.5, 0.5, 141, 4, 5),
     Case("12x12x4x8/6x6x2x4", (12, 12, 4, 8), (6, 6, 2, 4), 0.13, 1.5, 0.5, 151, 4, 5),
+]
+
+# Four or more domains in every direction, so the -mu and +mu neighbour
+# domains of every domain differ (with two per direction they coincide): the
+# neighbour and face indexing of each compiled domain shape.
+WIDE = [
+    Case("8^4/2^4", (8, 8, 8, 8), (2, 2, 2, 2), 0.13, 1.5, 0.5, 161, 8, 4),
+    Case("16^4/4^4", (16, 16, 16, 16), (4, 4, 4, 4), 0.13, 1.5, 0.5, 171, 8, 5),
+    Case("32x16x16x16/8x4^3", (32, 16, 16, 16), (8, 4, 4, 4), 0.1355, 1.5, 0.5, 181, 8, 5),
+    Case("16x16x16x32/4^3x8", (16, 16, 16, 32), (4, 4, 4, 8), 0.13, 1.5, 0.5, 191, 8, 5),
+    Case("24x24x8x16/6x6x2x4", (24, 24, 8, 16), (6, 6, 2, 4), 0.13, 1.5, 0.5, 199, 8, 5),
 ]
 
 # Block solves on 288-site domains run in 320-thread workgroups with idle
