@@ -49,7 +49,7 @@ def log(*a):
 class System:
     """One lattice of the benchmark with its sources (one or more right-hand sides)."""
 
-    def __init__(self, w, U, srcs, schedule="sweeps", schwarz="multiplicative"):
+    def __init__(self, w, U, srcs, schedule="sweeps", schwarz="multiplicative", product="lane"):
         import numpy as np
         import torch
 
@@ -59,13 +59,14 @@ class System:
         self.ctx = ddqcd.Context(w.lattice, w.domain, w.kappa, w.csw, w.bc)
         self.ctx.load_gauge(torch.from_numpy(U).to(dev))
         self.ctx.set_solver(w.restart, w.tol, 64)
-        self.ctx.set_sap(w.n_cycles, w.n_mr, w.prec)
+        self.product = product
+        self.ctx.set_sap(w.n_cycles, w.n_mr, w.prec, product)
         self.ctx.set_schedule(schedule)
         self.ctx.set_schwarz(schwarz)
         self.b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).to(dev)
 
 
-def build(name, schedule, tune=False, schwarz="multiplicative"):
+def build(name, schedule, tune=False, schwarz="multiplicative", domain=None, product="lane"):
     import dataclasses
 
     import numpy as np
@@ -87,13 +88,15 @@ def build(name, schedule, tune=False, schwarz="multiplicative"):
             out.append(System(w, U, [src], schedule, schwarz))
         return out
     w = configs.WORKLOADS[name]
+    if domain is not None:
+        w = dataclasses.replace(w, domain=domain)
     log(f"[bench] workload {w.name}: generating inputs")
     U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
     if w.nrhs > 1:   # point sources: every spin and colour at the origin
         srcs = [inputs.point_source(w.lattice, 0, s, c) for s in range(4) for c in range(3)][:w.nrhs]
     else:
         srcs = [inputs.gaussian_source(w.lattice, w.source_seed)]
-    return [System(w, U, srcs, schedule, schwarz)]
+    return [System(w, U, srcs, schedule, schwarz, product)]
 
 
 def solve_all(systems, ddqcd):
@@ -130,6 +133,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-preconditioner comparison solve")
     ap.add_argument("--schwarz", default="multiplicative", choices=["multiplicative", "additive"],
                     help="Schwarz method of the preconditioner (the workloads are defined with multiplicative)")
+    ap.add_argument("--domain", default=None,
+                    help="override the workload's domain shape, e.g. 4,4,4,4 (single-lattice workloads)")
+    ap.add_argument("--product", default="lane", choices=["lane", "tile", "mfma_f32", "mfma_bf16"],
+                    help="block-solve product form: one right-hand side per workgroup, or tiles of four with the "
+                         "link products on VALU, FP32 MFMA or BF16-input MFMA (4^4 domains, FP16 storage)")
     ap.add_argument("--no-tune", action="store_true",
                     help="uneven batch: keep the listed domain shapes instead of autotuning them per lattice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -146,7 +154,9 @@ def main():
     from paper_1412_2629_amd import ddqcd, geometry
 
     t_tune = time.perf_counter()
-    systems = build(args.workload, args.schedule, tune=not args.no_tune, schwarz=args.schwarz)
+    systems = build(args.workload, args.schedule, tune=not args.no_tune, schwarz=args.schwarz,
+                    domain=tuple(int(v) for v in args.domain.split(",")) if args.domain else None,
+                    product=args.product)
     t_tune = time.perf_counter() - t_tune
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
@@ -233,7 +243,7 @@ def main():
         wl = (f"{w0.name}: lattice {w0.lattice}, kappa {w0.kappa}, c_sw {w0.csw}, eps {w0.eps}, "
               f"domains {w0.domain}, SAP {w0.n_cycles} cycles x {w0.n_mr} MR ({w0.prec}), "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, {len(systems[0].srcs)} right-hand side(s), "
-              f"schedule {args.schedule}, {args.schwarz} Schwarz")
+              f"schedule {args.schedule}, {args.schwarz} Schwarz, block-solve products {args.product}")
         batch = len(systems[0].srcs)
     out = {
         "metric": METRIC,
@@ -302,6 +312,8 @@ def roofline(systems, achieved_tflops, launch_ms, traffic):
     alu_frac = achieved_tflops / FP32_PEAK_TFLOPS
     hbm_frac = gbs / HBM_PEAK_GBS
     kernel = "k_sap_lds" if w0.prec != "f64" else "k_sap_f64"
+    if systems[0].product != "lane":
+        kernel = "k_sap_tile"
     common = {"kernel": kernel, "traffic": traffic,
               "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE+WRITE_SIZE)",
               "algorithmic_bytes_per_launch": round(bytes_launch), "launch_ms": round(launch_ms, 5),
@@ -334,7 +346,7 @@ def fp64_comparison(systems, xs, iters, t_solve, ddqcd):
     torch.cuda.synchronize()
     t64 = time.perf_counter() - t1
     for s in systems:
-        s.ctx.set_sap(s.w.n_cycles, s.w.n_mr, s.w.prec)
+        s.ctx.set_sap(s.w.n_cycles, s.w.n_mr, s.w.prec, s.product)
     diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xs, x64))
     steps64 = [i["iters"] for i in i64]
     return {"fp64_sap_solve_s": round(t64, 5), "fp64_sap_fgcr_steps": steps64 if len(steps64) > 1 else steps64[0],

@@ -94,12 +94,35 @@ int ddqcd_create(const int lattice[4], const int domain[4], double kappa, double
 /* Frees the context and all device memory it owns.  NULL is allowed. */
 int ddqcd_destroy(ddqcd_t ctx);
 
+/* How the block solves form the SU(3) link x half-spinor products of their
+ * hops (the hop structure of Sec. II-B: project, multiply by the link,
+ * reconstruct).  DDQCD_PRODUCT_LANE: one right-hand side per workgroup, one
+ * site per thread, products on the vector ALUs.  The tile forms solve one
+ * domain for a tile of four right-hand sides of a lattice per workgroup (the
+ * link is staged once for the tile): DDQCD_PRODUCT_TILE_VALU with the products
+ * on the vector ALUs, DDQCD_PRODUCT_MFMA_F32 on FP32 matrix instructions
+ * (U in real form, 6x6, times the 6x4 block of the four right-hand sides'
+ * half-spinors, FP32 inputs and accumulation), DDQCD_PRODUCT_MFMA_BF16 on
+ * BF16-input matrix instructions with FP32 accumulation (link and half-spinor
+ * rounded to BF16 for the product).  The tile forms need 4x4x4x4 domains and
+ * DDQCD_FP16 storage; a solve or preconditioner call with nrhs right-hand sides
+ * uses ceil(nrhs / 4) tiles. */
+typedef enum {
+    DDQCD_PRODUCT_LANE = 0,
+    DDQCD_PRODUCT_TILE_VALU = 1,
+    DDQCD_PRODUCT_MFMA_F32 = 2,
+    DDQCD_PRODUCT_MFMA_BF16 = 3
+} ddqcd_product;
+
 /* Schwarz preconditioner settings: n_cycles = I_Schwarz >= 1, n_mr = I_domain
  * >= 1 (Sec. II-D), prec = storage/arithmetic of the block solves:
  * DDQCD_FP64, DDQCD_FP32, or DDQCD_FP16 (FP16 links, clover and spinors with
- * per-domain scales, FP32 arithmetic, FP32 solution accumulator).  Every
- * precision is available for every domain shape ddqcd_create accepts. */
-int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec);
+ * per-domain scales, FP32 arithmetic, FP32 solution accumulator); product = a
+ * ddqcd_product.  Every precision is available with DDQCD_PRODUCT_LANE for
+ * every domain shape ddqcd_create accepts, except FP64 on 6x6x2x4 domains.
+ * DDQCD_ERR_GEOMETRY for a combination without a kernel, DDQCD_ERR_ARG for
+ * values out of range. */
+int ddqcd_set_sap(ddqcd_t ctx, int n_cycles, int n_mr, int prec, int product);
 
 /* How the block solves of one preconditioner call are scheduled.
  * DDQCD_SCHED_SWEEPS (the default) launches one kernel per colour of each

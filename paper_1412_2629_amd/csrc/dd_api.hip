@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -46,7 +47,7 @@ struct Slot {
 // blocks are fetched into one L2.
 struct Plan {
     struct Group {
-        int shape = 0, prec = 0;
+        int shape = 0, prec = 0, product = 0;
         int2 *items[3] = {nullptr, nullptr, nullptr};   // black, white, all domains
         int nitems[3] = {0, 0, 0};
     };
@@ -73,7 +74,7 @@ constexpr size_t MAX_PLANS = 32;
 struct ddqcd_ctx {
     Geo g{};
     double kappa = 0, csw = 0;
-    int n_cycles = 16, n_mr = 5, sap_prec = DDQCD_FP32;
+    int n_cycles = 16, n_mr = 5, sap_prec = DDQCD_FP32, product = DDQCD_PRODUCT_LANE;
     int restart = 16, max_cycles = 64;
     double tol = 1e-10;
     int schedule = DDQCD_SCHED_SWEEPS;
@@ -206,8 +207,8 @@ std::string plan_key(const std::vector<Sys> &sys)
     char buf[160];
     for (const Sys &s : sys) {
         const Geo &g = s.c->g;
-        snprintf(buf, sizeof buf, "%p:%d:%d:%d,%d,%d,%d:%d,%d,%d,%d;", (void *)s.c, s.slot, s.c->sap_prec, g.L[0],
-                 g.L[1], g.L[2], g.L[3], g.b[0], g.b[1], g.b[2], g.b[3]);
+        snprintf(buf, sizeof buf, "%p:%d:%d:%d:%d,%d,%d,%d:%d,%d,%d,%d;", (void *)s.c, s.slot, s.c->sap_prec,
+                 s.c->product, g.L[0], g.L[1], g.L[2], g.L[3], g.b[0], g.b[1], g.b[2], g.b[3]);
         k += buf;
     }
     return k;
@@ -229,11 +230,11 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
     auto plan = std::make_unique<Plan>();
     HIPCHK(lead, hipMalloc(&plan->d_args, sizeof(SapArgs) * sys.size()));
     plan->h_args.resize(sys.size());
-    // group the systems by (domain shape, precision)
-    std::vector<std::pair<int, int>> gk;
+    // group the systems by (domain shape, precision, product form)
+    std::vector<std::array<int, 3>> gk;
     std::vector<std::vector<int>> members;
     for (size_t i = 0; i < sys.size(); i++) {
-        const std::pair<int, int> k{sap_shape_id(sys[i].c->g.b), sys[i].c->sap_prec};
+        const std::array<int, 3> k{sap_shape_id(sys[i].c->g.b), sys[i].c->sap_prec, sys[i].c->product};
         size_t gi = std::find(gk.begin(), gk.end(), k) - gk.begin();
         if (gi == gk.size()) {
             gk.push_back(k);
@@ -244,16 +245,34 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
     for (size_t gi = 0; gi < gk.size(); gi++) {
         plan->groups.emplace_back();
         Plan::Group &G = plan->groups.back();
-        G.shape = gk[gi].first;
-        G.prec = gk[gi].second;
-        const int ndw = sap_domains_per_workgroup(G.shape, G.prec);
+        G.shape = gk[gi][0];
+        G.prec = gk[gi][1];
+        G.product = gk[gi][2];
+        const int ndw = sap_domains_per_workgroup(G.shape, G.prec, G.product);
+        const int rt = sap_rhs_per_workgroup(G.product);
+        // tiles: up to rt systems of one context with consecutive system
+        // numbers (one system each for the one-right-hand-side kernels)
+        std::vector<std::pair<int, int>> tiles;   // (first system, count)
+        for (int si : members[gi]) {
+            if (!tiles.empty()) {
+                auto &tl = tiles.back();
+                const int last = tl.first + tl.second - 1;
+                if (tl.second < rt && si == last + 1 && sys[si].c == sys[last].c) {
+                    tl.second++;
+                    continue;
+                }
+            }
+            tiles.emplace_back(si, 1);
+        }
         for (int col = 0; col < 3; col++) {
-            // runs of ndw domains of one system (one workgroup each), one list
+            // runs of ndw domains of one tile (one workgroup each), one list
             // of runs per XCD; the runs of one (context, domain run) share a list
             std::vector<std::vector<std::vector<int2>>> lane(N_XCD);
             std::map<std::pair<ddqcd_t, int>, int> key_lane;
             int next = 0;
-            for (int si : members[gi]) {
+            for (const auto &tl : tiles) {
+                const int si = tl.first;
+                const int x = rt > 1 ? si | (tl.second << 24) : si;
                 std::vector<int> all_doms;
                 if (col == 2) {
                     all_doms = sys[si].c->dom_host[0];
@@ -267,7 +286,7 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
                     auto f = key_lane.find(kd);
                     const int ln = f == key_lane.end() ? (key_lane[kd] = next++ % N_XCD) : f->second;
                     std::vector<int2> run;
-                    for (int q = 0; q < ndw; q++) run.push_back(make_int2(si, doms[r * ndw + q]));
+                    for (int q = 0; q < ndw; q++) run.push_back(make_int2(x, doms[r * ndw + q]));
                     lane[ln].push_back(run);
                 }
             }
@@ -304,7 +323,8 @@ hipError_t enqueue_sweeps(const Plan &plan, int n_cycles, hipStream_t s)
             v.res_out = !v.last;
             v.flip = cyc & 1;
             for (const Plan::Group &G : plan.groups) {
-                hipError_t e = sap_sweep_batch(plan.d_args, G.items[2], G.nitems[2], G.shape, G.prec, v, s);
+                hipError_t e =
+                    sap_sweep_batch(plan.d_args, G.items[2], G.nitems[2], G.shape, G.prec, G.product, v, s);
                 if (e != hipSuccess) return e;
             }
         }
@@ -320,7 +340,8 @@ hipError_t enqueue_sweeps(const Plan &plan, int n_cycles, hipStream_t s)
             v.res_out = !v.last;
             v.flip = 0;
             for (const Plan::Group &G : plan.groups) {
-                hipError_t e = sap_sweep_batch(plan.d_args, G.items[col], G.nitems[col], G.shape, G.prec, v, s);
+                hipError_t e =
+                    sap_sweep_batch(plan.d_args, G.items[col], G.nitems[col], G.shape, G.prec, G.product, v, s);
                 if (e != hipSuccess) return e;
             }
         }
@@ -953,16 +974,20 @@ int ddqcd_destroy(ddqcd_t c)
     return DDQCD_OK;
 }
 
-int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec)
+int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec, int product)
 {
     if (!c) return DDQCD_ERR_ARG;
     if (n_cycles < 1 || n_mr < 1 || n_cycles > 1000 || n_mr > 1000) return fail(c, DDQCD_ERR_ARG, "bad SAP iteration counts");
     if (prec != DDQCD_FP64 && prec != DDQCD_FP32 && prec != DDQCD_FP16) return fail(c, DDQCD_ERR_ARG, "bad precision");
+    if (product < DDQCD_PRODUCT_LANE || product > DDQCD_PRODUCT_MFMA_BF16) return fail(c, DDQCD_ERR_ARG, "bad product form");
     if (!sap_prec_supported(c->g.b, prec))
         return fail(c, DDQCD_ERR_GEOMETRY, "no block-solve kernel for this domain shape and precision");
+    if (!sap_product_supported(c->g.b, prec, product))
+        return fail(c, DDQCD_ERR_GEOMETRY, "the right-hand-side tile forms need 4x4x4x4 domains and FP16 storage");
     c->n_cycles = n_cycles;
     c->n_mr = n_mr;
     c->sap_prec = prec;
+    c->product = product;
     return DDQCD_OK;
 }
 
@@ -1190,7 +1215,7 @@ int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const dou
     for (const std::vector<int> &bd : cand) {
         ddqcd_t c = nullptr;
         int st = ddqcd_create(lattice, bd.data(), kappa, c_sw, boundary, &c);
-        if (st == DDQCD_OK) st = ddqcd_set_sap(c, n_cycles, n_mr, prec);
+        if (st == DDQCD_OK) st = ddqcd_set_sap(c, n_cycles, n_mr, prec, DDQCD_PRODUCT_LANE);
         if (st == DDQCD_OK) st = ddqcd_set_solver(c, restart, tol, max_cycles);
         if (st == DDQCD_OK) st = ddqcd_load_gauge(c, U, stream);
         if (st == DDQCD_OK) st = ddqcd_solve(c, x, b, 1, 0, nullptr, stream);   // first call builds the plans

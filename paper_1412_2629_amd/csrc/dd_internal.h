@@ -69,17 +69,27 @@ bool sap_shape_supported(const int b[4]);
 bool sap_prec_supported(const int b[4], int prec);
 long sap_face_sites(const int b[4]);
 int sap_shape_id(const int b[4]);
-// Domains one block-solve workgroup takes for (shape, precision): the items
-// of a launch come in runs of this many domains of one system, and a run is
-// never split or padded.
-int sap_domains_per_workgroup(int shape, int prec);
+// How a block-solve workgroup forms the SU(3) products of its hops:
+// PRODUCT_LANE, one right-hand side per workgroup and one site per thread
+// (VALU); the TILE forms take a tile of four right-hand sides of one lattice
+// per workgroup (4^4 domains, FP16 storage) with the product on the VALU, on
+// FP32 MFMA, or on BF16-input MFMA with FP32 accumulation.
+enum { PRODUCT_LANE = 0, PRODUCT_TILE_VALU = 1, PRODUCT_TILE_MFMA_F32 = 2, PRODUCT_TILE_MFMA_BF16 = 3 };
+bool sap_product_supported(const int b[4], int prec, int product);
+// Right-hand sides one workgroup takes (1, or 4 for the tile forms): the items
+// of a tile launch are (first system | systems in the tile << 24, domain).
+int sap_rhs_per_workgroup(int product);
+// Domains one block-solve workgroup takes for (shape, precision, product): the
+// items of a launch come in runs of this many domains of one system, and a run
+// is never split or padded.
+int sap_domains_per_workgroup(int shape, int prec, int product);
 // The compiled domain shapes: ids 0 .. sap_shape_count() - 1 and their extents.
 int sap_shape_count();
 void sap_shape_extents(int shape, int b[4]);
 // One colour of one half-sweep for a list of (system, domain) items; args and
 // items are device arrays.  All systems share one domain shape (shape id).
-hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,
-                           hipStream_t s);
+hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, int product,
+                           Visit v, hipStream_t s);
 
 // ---- FP64 linear algebra on flat complex vectors (double2) ---------------
 struct Blas {

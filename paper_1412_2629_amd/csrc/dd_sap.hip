@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "dd_device.h"
@@ -435,7 +436,7 @@ __device__ __forceinline__ void face_fetch(const SapArgs &a, const int D[4], con
     w = sc * T(wrap ? 0.5 * a.g.bc[MU] : 0.5);
 }
 
-template <class Sh, int MU, typename T, typename G, int NLC, int LNLC, bool FROM_LDS>
+template <class Sh, int MU, typename T, typename G, int NLC, int LNLC, bool FROM_LDS, int LSTR = Sh::VD>
 __device__ __forceinline__ void face_apply(const SapArgs &a, int d, int loc, const v2<G> *slink, const cx<T> h[6],
                                            T w, int side, cx<T> rho[12])
 {
@@ -445,14 +446,15 @@ __device__ __forceinline__ void face_apply(const SapArgs &a, int d, int loc, con
     } else if (side == 2) {
         cx<T> uh[6];
         su3<T> U;
-        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD);
+        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * LSTR + loc, LSTR);
         else U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_mul(U, h, uh);
         recon_acc<MU, -1>(rho, uh, w);
     }
 }
 
-template <class Sh, int MU, typename T, typename SS, typename G, int NLC, int LNLC = NLC, bool FROM_LDS = false>
+template <class Sh, int MU, typename T, typename SS, typename G, int NLC, int LNLC = NLC, bool FROM_LDS = false,
+          int LSTR = Sh::VD>
 __device__ __forceinline__ void write_face(const SapArgs &a, int d, const int l[4], int loc, const cx<T> delta[12],
                                            T inv_sc, const v2<G> *slink = nullptr)
 {
@@ -468,9 +470,9 @@ __device__ __forceinline__ void write_face(const SapArgs &a, int d, const int l[
     } else if (l[MU] == Sh::B[MU] - 1) {
         cx<T> uh[6];
         proj<MU, +1>(delta, h);
-        // FROM_LDS: the domain's links staged in slink ([mu][LNLC][VD]), else global
+        // FROM_LDS: the domain's links staged in slink ([mu][LNLC][LSTR]), else global
         su3<T> U;
-        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * VD + loc, VD);
+        if constexpr (FROM_LDS) U = ld_link<T, G, LNLC>(slink, (long)MU * LNLC * LSTR + loc, LSTR);
         else U = ld_link<T, G, NLC>((const v2<G> *)a.links, ((long)d * 4 + MU) * NLC * VD + loc, VD);
         su3_dag_mul(U, h, uh);
         long fb = face_base<Sh>(d, 2 * MU + 1);
@@ -1211,6 +1213,455 @@ __global__ __launch_bounds__(Sh::VH) void k_sap_sweep(const SapArgs *args, const
 
 // ---- dispatch ---------------------------------------------------------------
 
+// ---- block solves of a tile of right-hand sides ---------------------------------
+//
+// One workgroup solves one domain for a tile of up to RT = 4 right-hand sides
+// of one lattice (systems sys0 .. sys0 + nt - 1), so the domain's links are
+// staged into LDS once for the tile and each link entry read from LDS serves
+// all of them.  Thread t works on the even and the odd site with half index
+// h = t / 4 for right-hand side r = t % 4, so the four threads of a site are
+// four consecutive lanes, and every thread is busy in both parity phases of
+// the MR step.  Spinors in LDS are [component][half index][right-hand side].
+//
+// Those four lanes are one 4x4 block of the 16-block MFMA instructions.  In
+// a hop, the SU(3) product U h (U the link or its adjoint, h the projected
+// half-spinor) is, in real form, a 6x6 matrix (rows Re y_a and Im y_a, columns
+// Re h_b and Im h_b) times a 6-vector; for the four right-hand sides and one
+// spin component of h it is a 6x6 times 6x4 product, done as two 4-row blocks
+// of the site's quad: lane r supplies row r of each block of U and column r
+// (its own half-spinor), and receives column r of the result.  PROD selects
+// the product: VALU (per-thread fused multiply-adds, as in k_sap_lds), FP32
+// MFMA (4x4x1, six steps over the inner dimension) or BF16-input MFMA with
+// FP32 accumulation (4x4x4, two steps; the link and half-spinor rounded to
+// BF16).  Lanes of right-hand sides beyond the tile work on zeros and touch no
+// memory.
+
+enum { PROD_VALU = 0, PROD_MFMA_F32 = 1, PROD_MFMA_BF16 = 2 };
+constexpr int RT = 4;
+// Link entries in LDS lie LSTR = VD + 16 entries apart: the four lanes of a
+// quad read four different entries of one site (rows or columns of U for the
+// matrix operands), and with a stride of VD (a multiple of the 64 banks) all
+// four would fall in one bank.
+template <class Sh> constexpr int tile_lstr() { return Sh::VD + 16; }
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+
+// sum of v over the threads of this thread's right-hand side (lanes with equal
+// lane % 4), for all NW waves of the workgroup; fixed order, every thread joins
+template <int NW, int N> __device__ __forceinline__ void rhs_sum(float (&v)[N], float *red)
+{
+#pragma unroll
+    for (int q = 0; q < N; q++)
+#pragma unroll
+        for (int o = 4; o < 64; o <<= 1) v[q] += __shfl_xor(v[q], o);
+    const int w = threadIdx.x >> 6, r = threadIdx.x & 3;
+    if ((threadIdx.x & 63) < RT)
+#pragma unroll
+        for (int q = 0; q < N; q++) red[(w * RT + r) * N + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; q++) {
+        float s = 0;
+        for (int k = 0; k < NW; k++) s += red[(k * RT + r) * N + q];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+template <int NW> __device__ __forceinline__ float rhs_max(float v, float *red)
+{
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    const int w = threadIdx.x >> 6, r = threadIdx.x & 3;
+    if ((threadIdx.x & 63) < RT) red[w * RT + r] = v;
+    __syncthreads();
+    float m = red[r];
+    for (int k = 1; k < NW; k++) m = fmax(m, red[k * RT + r]);
+    __syncthreads();
+    return m;
+}
+
+// Row `row` of U (forward hop, SIGN < 0) or of U^dagger (backward hop): u[b] =
+// U[row][b], or conj(U[b][row]); links in LDS as three rows [mu][9][VD].
+template <class Sh, int SIGN, typename G>
+__device__ __forceinline__ void link_row(const v2<G> *slink, int mu, int lloc, int row, cx<float> u[3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const int e = SIGN < 0 ? row * 3 + b : b * 3 + row;
+        const v2<G> v = slink[(mu * 9 + e) * tile_lstr<Sh>() + lloc];
+        u[b] = {static_cast<float>(v.x), SIGN < 0 ? static_cast<float>(v.y) : -static_cast<float>(v.y)};
+    }
+}
+
+// uh = (U or U^dagger) h for the four right-hand sides of the quad (h: this
+// lane's half-spinor, both spin components) on the matrix cores.
+template <class Sh, int SIGN, int PROD, typename G>
+__device__ __forceinline__ void quad_product(const v2<G> *slink, int mu, int lloc, int r, const cx<float> h[6],
+                                             cx<float> uh[6])
+{
+    // block 0 rows: Re y_0, Re y_1, Re y_2, Im y_0; block 1: Im y_1, Im y_2, 0, 0
+    cx<float> u0[3], u1[3];
+    link_row<Sh, SIGN, G>(slink, mu, lloc, r < 3 ? r : 0, u0);
+    link_row<Sh, SIGN, G>(slink, mu, lloc, r == 0 ? 1 : 2, u1);
+    const bool re0 = r < 3, use1 = r < 2;
+    float a0[6], a1[6];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        a0[b] = re0 ? u0[b].r : u0[b].i;
+        a0[3 + b] = re0 ? -u0[b].i : u0[b].r;
+        a1[b] = use1 ? u1[b].i : 0.f;
+        a1[3 + b] = use1 ? u1[b].r : 0.f;
+    }
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; s++) acc[s][0] = acc[s][1] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    if constexpr (PROD == PROD_MFMA_F32) {
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                const float bk = k < 3 ? h[s * 3 + k].r : h[s * 3 + k - 3].i;
+                acc[s][0] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0[k], bk, acc[s][0], 0, 0, 0);
+                acc[s][1] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1[k], bk, acc[s][1], 0, 0, 0);
+            }
+    } else {
+        const bf16x4_t A0lo = {(__bf16)a0[0], (__bf16)a0[1], (__bf16)a0[2], (__bf16)a0[3]};
+        const bf16x4_t A0hi = {(__bf16)a0[4], (__bf16)a0[5], (__bf16)0.f, (__bf16)0.f};
+        const bf16x4_t A1lo = {(__bf16)a1[0], (__bf16)a1[1], (__bf16)a1[2], (__bf16)a1[3]};
+        const bf16x4_t A1hi = {(__bf16)a1[4], (__bf16)a1[5], (__bf16)0.f, (__bf16)0.f};
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const cx<float> *hs = h + 3 * s;
+            const bf16x4_t Blo = {(__bf16)hs[0].r, (__bf16)hs[1].r, (__bf16)hs[2].r, (__bf16)hs[0].i};
+            const bf16x4_t Bhi = {(__bf16)hs[1].i, (__bf16)hs[2].i, (__bf16)0.f, (__bf16)0.f};
+            acc[s][0] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A0lo, Blo, acc[s][0], 0, 0, 0);
+            acc[s][0] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A0hi, Bhi, acc[s][0], 0, 0, 0);
+            acc[s][1] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A1lo, Blo, acc[s][1], 0, 0, 0);
+            acc[s][1] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A1hi, Bhi, acc[s][1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        uh[s * 3 + 0] = {acc[s][0][0], acc[s][0][3]};
+        uh[s * 3 + 1] = {acc[s][0][1], acc[s][1][0]};
+        uh[s * 3 + 2] = {acc[s][0][2], acc[s][1][1]};
+    }
+}
+
+// acc += the in-domain hop into site l (local index loc) along MU; SIGN < 0:
+// from x + mu with (1 - gamma_mu) U_mu(x), SIGN > 0: from x - mu with
+// (1 + gamma_mu) U_mu(x - mu)^dagger.  v holds the other parity's sites.
+template <class Sh, int MU, int SIGN, int PROD, typename G>
+__device__ __forceinline__ void tile_hop(const cx<float> (*v)[Sh::VH][RT], const int l[4], int loc, int r,
+                                         const v2<G> *slink, cx<float> acc[12])
+{
+    constexpr int VH = Sh::VH;
+    const bool has = SIGN < 0 ? l[MU] + 1 < Sh::B[MU] : l[MU] > 0;
+    int n[4] = {l[0], l[1], l[2], l[3]};
+    if (has) n[MU] += SIGN < 0 ? 1 : -1;
+    const int nh = Sh::half_index(n);   // without a neighbour: a valid index, its value unused
+    const int lloc = SIGN < 0 ? loc : (1 - (loc >= VH)) * VH + nh;
+    cx<float> s[12], h[6], uh[6];
+    if constexpr (PROD == PROD_VALU) {
+        if (!has) return;
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = v[k][nh][r];
+        proj<MU, SIGN>(s, h);
+        const su3<float> U = ld_link<float, G, 9>(slink, (long)MU * 9 * tile_lstr<Sh>() + lloc, tile_lstr<Sh>());
+        if constexpr (SIGN < 0) su3_mul(U, h, uh);
+        else su3_dag_mul(U, h, uh);
+        recon_acc<MU, SIGN>(acc, uh, 1.0f);
+    } else {
+        // every lane takes part in the matrix instructions; a site without this
+        // neighbour multiplies a finite stand-in (its own index's entry) and
+        // adds the product with weight 0
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = v[k][nh][r];
+        proj<MU, SIGN>(s, h);
+        quad_product<Sh, SIGN, PROD, G>(slink, MU, lloc, r, h, uh);
+        recon_acc<MU, SIGN>(acc, uh, has ? 1.0f : 0.0f);
+    }
+}
+
+template <class Sh, int PROD, typename G>
+__device__ __forceinline__ void tile_hops(const cx<float> (*v)[Sh::VH][RT], const int l[4], int loc, int r,
+                                          const v2<G> *slink, cx<float> acc[12])
+{
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = czero<float>();
+    if constexpr (PROD != PROD_VALU) {
+        // one hop's operands live at a time (a loop the compiler keeps rolled)
+#pragma unroll 1
+        for (int k = 0; k < 8; k++) {
+            switch (k) {
+                case 0: tile_hop<Sh, 0, -1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 1: tile_hop<Sh, 0, +1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 2: tile_hop<Sh, 1, -1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 3: tile_hop<Sh, 1, +1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 4: tile_hop<Sh, 2, -1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 5: tile_hop<Sh, 2, +1, PROD, G>(v, l, loc, r, slink, acc); break;
+                case 6: tile_hop<Sh, 3, -1, PROD, G>(v, l, loc, r, slink, acc); break;
+                default: tile_hop<Sh, 3, +1, PROD, G>(v, l, loc, r, slink, acc); break;
+            }
+        }
+        return;
+    }
+    tile_hop<Sh, 0, -1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 0, +1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 1, -1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 1, +1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 2, -1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 2, +1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 3, -1, PROD, G>(v, l, loc, r, slink, acc);
+    tile_hop<Sh, 3, +1, PROD, G>(v, l, loc, r, slink, acc);
+}
+
+// Items: x = first system of the tile | (systems in the tile) << 24, y = domain.
+// SS: storage of block residual and boundary terms; G: links and clover (two
+// rows stored, three rows in LDS); arithmetic and accumulator FP32.
+template <class Sh, int PROD, typename SS, typename G, bool SCALED>
+__global__ __launch_bounds__(Sh::VH * RT) void k_sap_tile(const SapArgs *args, const int2 *items, Visit v)
+{
+    using T = float;
+    using PS = float;
+    constexpr int VD = Sh::VD, VH = Sh::VH, NT = VH * RT, NW = NT / 64, NLC = 6, LNLC = 9;
+    static_assert(NT % 64 == 0 && NT <= 1024 && NT == 2 * VD, "whole waves; two threads per site for staging");
+    constexpr int LSTR = tile_lstr<Sh>();
+    __shared__ v2<G> slink[4 * LNLC * LSTR];   // [mu][9][LSTR]
+    __shared__ v2<G> sclo[36][VH];            // C_o^-1 of the odd sites
+    __shared__ cx<T> she[12][VH][RT];
+    __shared__ cx<T> sho[12][VH][RT];
+    __shared__ T red[NW * RT * 3];
+
+    const int2 it = items[blockIdx.x];
+    const int sys0 = it.x & 0xffffff, nt = it.x >> 24, d = it.y;
+    const int t = threadIdx.x, hi = t >> 2, r = t & 3;
+    // this lane's right-hand side; what the tile shares (geometry, links,
+    // clover, MR steps) is taken from the first system, so it stays uniform
+    const SapArgs &a0 = args[sys0];
+    SapArgs a = args[sys0 + (r < nt ? r : 0)];
+    a.g = a0.g;
+    a.links = a0.links;
+    a.cs = a0.cs;
+    a.n_mr = a0.n_mr;
+    const bool live = r < nt && a.active;
+    bind_faces(a, v);
+    const int loc_e = hi, loc_o = VH + hi;
+    int le[4], lo[4];
+    Sh::coords(loc_e, le);
+    Sh::coords(loc_o, lo);
+    int D[4];
+    {
+        int q = d;
+        D[0] = q % a.g.n[0]; q /= a.g.n[0];
+        D[1] = q % a.g.n[1]; q /= a.g.n[1];
+        D[2] = q % a.g.n[2];
+        D[3] = q / a.g.n[2];
+    }
+    const v2<G> *glinks = (const v2<G> *)a.links;
+    const v2<G> *cs = (const v2<G> *)a.cs;
+
+    // ---- links and the odd sites' C_o^-1 into LDS (two threads per site, two
+    // link directions each), the even site's C_e into registers; every global
+    // load before the first LDS store
+    v2<G> cle[36];
+    {
+        const int q = t % VD, m0 = (t / VD) * 2;
+        v2<G> lt[2 * NLC];
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int e = 0; e < NLC; e++) lt[j * NLC + e] = glinks[(((long)d * 4 + m0 + j) * NLC + e) * VD + q];
+        const long cb = (long)d * 36 * VD;
+#pragma unroll
+        for (int k = 0; k < 36; k++) cle[k] = cs[cb + (long)k * VD + loc_e];
+        constexpr int NCO = 36 * VH / NT;
+        static_assert(36 * VH % NT == 0, "odd clover entries per thread");
+        v2<G> ct[NCO];
+#pragma unroll
+        for (int j = 0; j < NCO; j++) {
+            const int i = t + j * NT, k = i / VH;
+            ct[j] = cs[cb + (long)k * VD + VH + (i - k * VH)];
+        }
+#pragma unroll
+        for (int j = 0; j < NCO; j++) {
+            const int i = t + j * NT, k = i / VH;
+            sclo[k][i - k * VH] = ct[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const su3<T> U = ld_link<T, G, NLC>(lt + j * NLC, 0, 1);
+#pragma unroll
+            for (int e = 0; e < 9; e++) st<T, G>(slink, (long)((m0 + j) * 9 + e) * LSTR + q, U.m[e]);
+        }
+    }
+
+    // ---- the block right-hand side of both sites
+    cx<T> Ae[12], Ao[12], P[12], tt[12];
+    const long se = (long)d * 12 * VD + loc_e, so = (long)d * 12 * VD + loc_o;
+    if (!live) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) Ae[k] = Ao[k] = czero<T>();
+    } else if (v.first) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            Ae[k] = ld<T, double>(a.eta, se + (long)k * VD);
+            Ao[k] = ld<T, double>(a.eta, so + (long)k * VD);
+        }
+    } else {
+        const T sc = SCALED ? T(a.res_scale[d]) : T(1);
+        const v2<SS> *res = (const v2<SS> *)a.res;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            Ae[k] = scal(sc, ld<T, SS>(res, ((long)d * 12 + k) * VH + hi));
+            Ao[k] = czero<T>();
+        }
+    }
+    __syncthreads();   // links staged
+    if (v.faces_in && live) {
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            const int *l = p ? lo : le;
+            const int loc = p ? loc_o : loc_e;
+            cx<T> *A = p ? Ao : Ae;
+            cx<T> hf[4][6];
+            T wf[4] = {0, 0, 0, 0};
+            int sf[4];
+            face_fetch<Sh, 0, T, SS, SCALED>(a, D, l, hf[0], wf[0], sf[0]);
+            face_fetch<Sh, 1, T, SS, SCALED>(a, D, l, hf[1], wf[1], sf[1]);
+            face_fetch<Sh, 2, T, SS, SCALED>(a, D, l, hf[2], wf[2], sf[2]);
+            face_fetch<Sh, 3, T, SS, SCALED>(a, D, l, hf[3], wf[3], sf[3]);
+            face_apply<Sh, 0, T, G, NLC, LNLC, true, LSTR>(a, d, loc, slink, hf[0], wf[0], sf[0], A);
+            face_apply<Sh, 1, T, G, NLC, LNLC, true, LSTR>(a, d, loc, slink, hf[1], wf[1], sf[1], A);
+            face_apply<Sh, 2, T, G, NLC, LNLC, true, LSTR>(a, d, loc, slink, hf[2], wf[2], sf[2], A);
+            face_apply<Sh, 3, T, G, NLC, LNLC, true, LSTR>(a, d, loc, slink, hf[3], wf[3], sf[3], A);
+        }
+    }
+
+    // ---- even-odd preparation: r = rho_e - D_eo C_o^-1 rho_o, x = 0.  With
+    // the matrix-instruction products rho_o waits in this right-hand side's
+    // global buffer until the reconstruction (their operands leave no room
+    // for it in registers); the VALU form keeps it in registers.
+    constexpr bool PARK = PROD != PROD_VALU;
+    clover_apply<T, G>(&sclo[0][0], hi, VH, Ao, P);
+    v2<T> *rho_g = (v2<T> *)a.rho_tmp;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        sho[k][hi][r] = P[k];
+        if (PARK && live) st<T, T>(rho_g, ((long)d * 12 + k) * VH + hi, Ao[k]);
+    }
+    __syncthreads();
+    tile_hops<Sh, PROD, G>(sho, le, loc_e, r, slink, tt);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        she[k][hi][r] = Ae[k] + scal(T(0.5), tt[k]);
+        Ae[k] = czero<T>();
+    }
+
+    // ---- minimal residual on the Schur complement, per right-hand side
+#pragma unroll 1
+    for (int itr = 0; itr < a.n_mr; itr++) {
+        if constexpr (sizeof(v2<G>) == 4) {
+            // keep the clover blocks in their 16-bit storage form (see k_sap_lds)
+#pragma unroll
+            for (int q = 0; q < 36; q++) asm volatile("" : "+v"(cle[q]));
+        }
+        __syncthreads();
+        tile_hops<Sh, PROD, G>(she, lo, loc_o, r, slink, tt);
+#pragma unroll
+        for (int k = 0; k < 12; k++) tt[k] = scal(T(-0.5), tt[k]);   // D_oe r
+        clover_apply<T, G>(&sclo[0][0], hi, VH, tt, P);             // C_o^-1 D_oe r
+#pragma unroll
+        for (int k = 0; k < 12; k++) sho[k][hi][r] = P[k];
+        __syncthreads();
+        tile_hops<Sh, PROD, G>(sho, le, loc_e, r, slink, tt);
+        cx<T> rr[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) rr[k] = she[k][hi][r];
+        clover_reg<T, G>(cle, rr, P);                               // C_e r
+        T dots[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            P[k] = P[k] + scal(T(0.5), tt[k]);                      // p = C_e r - D_eo C_o^-1 D_oe r
+            dots[0] = fmad(P[k].i, rr[k].i, fmad(P[k].r, rr[k].r, dots[0]));
+            dots[1] = fmad(-P[k].i, rr[k].r, fmad(P[k].r, rr[k].i, dots[1]));
+            dots[2] = fmad(P[k].i, P[k].i, fmad(P[k].r, P[k].r, dots[2]));
+        }
+        rhs_sum<NW, 3>(dots, red);
+        const cx<T> alpha = dots[2] > T(0) ? cx<T>{dots[0] / dots[2], dots[1] / dots[2]} : czero<T>();
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            Ae[k] = cmac(Ae[k], alpha, rr[k]);
+            she[k][hi][r] = cmac(rr[k], neg(alpha), P[k]);
+        }
+    }
+
+    // ---- odd sites: delta_o = C_o^-1 (rho_o - D_oe x); x goes through sho
+#pragma unroll
+    for (int k = 0; k < 12; k++) sho[k][hi][r] = Ae[k];
+    __syncthreads();
+    tile_hops<Sh, PROD, G>(sho, lo, loc_o, r, slink, tt);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const cx<T> ro = !PARK ? Ao[k] : live ? ld<T, T>(rho_g, ((long)d * 12 + k) * VH + hi) : czero<T>();
+        tt[k] = ro + scal(T(0.5), tt[k]);
+    }
+    clover_apply<T, G>(&sclo[0][0], hi, VH, tt, Ao);                // Ao = delta_o, Ae = delta_e = x
+
+    // ---- epilogue: psi += delta, stored residual, boundary terms
+    if (live) {
+        const v2<PS> *psi_in = (const v2<PS> *)a.psi;
+        v2<PS> *psi_out = (v2<PS> *)a.psi;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            const long sb = p ? so : se;
+            const cx<T> *A = p ? Ao : Ae;
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                const cx<T> ps = v.first ? A[k] : ld<T, PS>(psi_in, sb + (long)k * VD) + A[k];
+                if (v.last) st<T, double>(a.out, sb + (long)k * VD, ps);
+                else st<T, PS>(psi_out, sb + (long)k * VD, ps);
+            }
+        }
+    }
+    if (v.res_out) {
+        cx<T> rr[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) rr[k] = she[k][hi][r];
+        T sc = T(1);
+        if constexpr (SCALED) {
+            sc = pow2_ceil(rhs_max<NW>(maxabs12(rr), red));
+            if (hi == 0 && live) a.res_scale[d] = (float)sc;
+        }
+        if (live) {
+            v2<SS> *res = (v2<SS> *)a.res;
+            const T inv = T(1) / sc;
+#pragma unroll
+            for (int k = 0; k < 12; k++) st<T, SS>(res, ((long)d * 12 + k) * VH + hi, scal(inv, rr[k]));
+        }
+    }
+    if (v.faces_out) {
+        T sc = T(1);
+        if constexpr (SCALED) {
+            sc = T(8) * pow2_ceil(rhs_max<NW>(fmax(maxabs12(Ae), maxabs12(Ao)), red));
+            if (hi == 0 && live) a.face_scale[d] = (float)sc;
+        }
+        const T inv = T(1) / sc;
+        if (live) {
+            write_face<Sh, 0, T, SS, G, NLC, LNLC, true, LSTR>(a, d, le, loc_e, Ae, inv, slink);
+            write_face<Sh, 1, T, SS, G, NLC, LNLC, true, LSTR>(a, d, le, loc_e, Ae, inv, slink);
+            write_face<Sh, 2, T, SS, G, NLC, LNLC, true, LSTR>(a, d, le, loc_e, Ae, inv, slink);
+            write_face<Sh, 3, T, SS, G, NLC, LNLC, true, LSTR>(a, d, le, loc_e, Ae, inv, slink);
+            write_face<Sh, 0, T, SS, G, NLC, LNLC, true, LSTR>(a, d, lo, loc_o, Ao, inv, slink);
+            write_face<Sh, 1, T, SS, G, NLC, LNLC, true, LSTR>(a, d, lo, loc_o, Ao, inv, slink);
+            write_face<Sh, 2, T, SS, G, NLC, LNLC, true, LSTR>(a, d, lo, loc_o, Ao, inv, slink);
+            write_face<Sh, 3, T, SS, G, NLC, LNLC, true, LSTR>(a, d, lo, loc_o, Ao, inv, slink);
+        }
+    }
+}
+
 // Every block-solve launch goes through here: the workgroup size must not
 // exceed the kernel's launch bound (the register allocation is made for that
 // bound), which is read from the code object once per kernel and checked on
@@ -1239,8 +1690,28 @@ static hipError_t launch_bounded(void (*kernel)(P...), unsigned grid, unsigned b
 }
 
 template <class Sh>
-static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, Visit v, hipStream_t s)
+static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitems, int prec, int product, Visit v,
+                               hipStream_t s)
 {
+    if (product != PRODUCT_LANE) {
+        // a tile of right-hand sides per workgroup: 4^4 domains, FP16 storage
+        if constexpr (std::is_same<Sh, Shape<4, 4, 4, 4>>::value) {
+            if (prec != P16) return hipErrorInvalidValue;
+            constexpr int NT = Sh::VH * RT;
+            switch (product) {
+                case PRODUCT_TILE_VALU:
+                    return launch_bounded(k_sap_tile<Sh, PROD_VALU, half_t, half_t, true>, nitems, NT, s, args, items, v);
+                case PRODUCT_TILE_MFMA_F32:
+                    return launch_bounded(k_sap_tile<Sh, PROD_MFMA_F32, half_t, half_t, true>, nitems, NT, s, args, items,
+                                          v);
+                case PRODUCT_TILE_MFMA_BF16:
+                    return launch_bounded(k_sap_tile<Sh, PROD_MFMA_BF16, half_t, half_t, true>, nitems, NT, s, args,
+                                          items, v);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if (prec == P64) {
         // FP64: one thread per even/odd site pair on 2^4 domains, else the LDS
         // layout (whole waves only: no FP64 kernel for padded workgroups)
@@ -1264,7 +1735,19 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
     }
 }
 
-int sap_domains_per_workgroup(int shape, int prec) { return shape == 0 && prec != P64 ? 8 : 1; }
+int sap_domains_per_workgroup(int shape, int prec, int product)
+{
+    return shape == 0 && prec != P64 && product == PRODUCT_LANE ? 8 : 1;
+}
+
+int sap_rhs_per_workgroup(int product) { return product == PRODUCT_LANE ? 1 : RT; }
+
+bool sap_product_supported(const int b[4], int prec, int product)
+{
+    if (product == PRODUCT_LANE) return sap_prec_supported(b, prec);
+    if (product < PRODUCT_TILE_VALU || product > PRODUCT_TILE_MFMA_BF16) return false;
+    return sap_shape_id(b) == 1 && prec == P16;
+}
 
 int sap_shape_id(const int b[4])
 {
@@ -1301,16 +1784,16 @@ long sap_face_sites(const int b[4])
     return 2 * (Vd / b[0] + Vd / b[1] + Vd / b[2] + Vd / b[3]);
 }
 
-hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, Visit v,
-                           hipStream_t s)
+hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, int product,
+                           Visit v, hipStream_t s)
 {
     if (nitems <= 0) return hipSuccess;
     switch (shape) {
-        case 0: return launch_batch<Shape<2, 2, 2, 2>>(args, items, nitems, prec, v, s);
-        case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, v, s);
-        case 2: return launch_batch<Shape<8, 4, 4, 4>>(args, items, nitems, prec, v, s);
-        case 3: return launch_batch<Shape<4, 4, 4, 8>>(args, items, nitems, prec, v, s);
-        case 4: return launch_batch<Shape<6, 6, 2, 4>>(args, items, nitems, prec, v, s);
+        case 0: return launch_batch<Shape<2, 2, 2, 2>>(args, items, nitems, prec, product, v, s);
+        case 1: return launch_batch<Shape<4, 4, 4, 4>>(args, items, nitems, prec, product, v, s);
+        case 2: return launch_batch<Shape<8, 4, 4, 4>>(args, items, nitems, prec, product, v, s);
+        case 3: return launch_batch<Shape<4, 4, 4, 8>>(args, items, nitems, prec, product, v, s);
+        case 4: return launch_batch<Shape<6, 6, 2, 4>>(args, items, nitems, prec, product, v, s);
         default: return hipErrorInvalidValue;
     }
 }

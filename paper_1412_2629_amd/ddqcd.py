@@ -16,6 +16,7 @@ FP64, FP32, FP16 = 0, 1, 2
 PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
 
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
+PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
            "ddqcd_set_solver", "ddqcd_load_gauge",
@@ -51,7 +52,7 @@ def lib():
         vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.ddqcd_create.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), d, d, ctypes.POINTER(d), ctypes.POINTER(vp)]
         L.ddqcd_destroy.argtypes = [vp]
-        L.ddqcd_set_sap.argtypes = [vp, i, i, i]
+        L.ddqcd_set_sap.argtypes = [vp, i, i, i, i]
         L.ddqcd_set_solver.argtypes = [vp, i, d, i]
         L.ddqcd_set_schedule.argtypes = [vp, i]
         L.ddqcd_set_schwarz.argtypes = [vp, i]
@@ -123,8 +124,11 @@ class Context:
         if st != OK:
             raise DDQCDError(st, f"{what}: {status_string(st)}: {lib().ddqcd_last_error(self._h).decode()}")
 
-    def set_sap(self, n_cycles=16, n_mr=5, prec="f32"):
-        self._check(lib().ddqcd_set_sap(self._h, n_cycles, n_mr, PREC[prec]), "set_sap")
+    def set_sap(self, n_cycles=16, n_mr=5, prec="f32", product="lane"):
+        """product: "lane" (one right-hand side per workgroup), "tile" (four per
+        workgroup, VALU products), "mfma_f32" or "mfma_bf16" (four per workgroup,
+        link products on matrix instructions)."""
+        self._check(lib().ddqcd_set_sap(self._h, n_cycles, n_mr, PREC[prec], PRODUCT[product]), "set_sap")
 
     def set_schedule(self, schedule):
         """"sweeps" (one launch per colour of a half-sweep), "graph" (the same launches replayed

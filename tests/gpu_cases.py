@@ -34,6 +34,13 @@ def site_err(got, want):
 # SITE_FACTOR times that relative to the RMS site norm.
 SAP_TOL = {"f64": 1e-12, "f32": 8 * 2.0 ** -24, "f16": 4 * 2.0 ** -11}
 SITE_FACTOR = 4.0
+# The tile forms of the FP16-storage block solve (ddqcd_set_sap product):
+# VALU and FP32-MFMA products keep the FP16 bound; BF16-input MFMA rounds the
+# link and the projected half-spinor to BF16 (u = 2^-8) in every product, a
+# relative perturbation of the block operator of at most about 2u per
+# application, which the block solve passes on to its output: 2 u_bf16.
+PRODUCT_TOL = {"lane": SAP_TOL["f16"], "tile": SAP_TOL["f16"], "mfma_f32": SAP_TOL["f16"],
+               "mfma_bf16": 2 * 2.0 ** -8}
 
 
 def dev(a):

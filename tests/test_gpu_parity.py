@@ -10,7 +10,8 @@ Tolerances (normwise relative errors):
 import numpy as np
 import pytest
 
-from tests.gpu_cases import BC, NO_FP64_SAP, SAP_TOL, SITE_FACTOR, SMALL, Case, dev, fp64_sap, host, rel, site_err
+from tests.gpu_cases import (BC, NO_FP64_SAP, PRODUCT_TOL, SAP_TOL, SITE_FACTOR, SMALL, WIDE, Case, dev, fp64_sap, host,
+                             rel, site_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -299,3 +300,91 @@ def test_bicgstab(case, oracle):
     assert st0 == 0 and info0["iters"] == 0 and not np.any(host(z))
     x2, info2, st2 = ctx.solve_bicgstab(dev(f), x0=dev(x))
     assert st2 == 0 and info2["iters"] == 0
+
+
+# ---------------------------------------------------------------------------
+# tiles of four right-hand sides per workgroup, link products on VALU or MFMA
+# ---------------------------------------------------------------------------
+
+TILE_PRODUCTS = ["tile", "mfma_f32", "mfma_bf16"]
+_tile_refs = {}
+
+
+def tile_reference(case, oracle, n):
+    """n seeded sources of the case and the oracle's SAP of each."""
+    if case.name not in _tile_refs:
+        etas = np.stack([case.source(60 + k) for k in range(n)])
+        want = [oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, e) for e in etas]
+        _tile_refs[case.name] = (etas, want)
+    return _tile_refs[case.name]
+
+
+@pytest.mark.parametrize("case", [SMALL[2], WIDE[1]], ids=repr)
+@pytest.mark.parametrize("product", TILE_PRODUCTS)
+def test_sap_tile(case, product, oracle):
+    """Five right-hand sides (a full tile and a tile of one) against the
+    oracle's SAP of each; a right-hand side solved alone (a tile of one) gives
+    the bits it gets inside a full tile."""
+    etas, want = tile_reference(case, oracle, 5)
+    ctx = case.context()
+    ctx.set_sap(case.n_cycles, case.n_mr, "f16", product)
+    got = host(ctx.sap(dev(etas)))
+    tol = PRODUCT_TOL[product]
+    for k in range(len(etas)):
+        err, site = site_err(got[k], want[k])
+        print(f"{case} {product} rhs {k}: error {err:.3e}, largest site error {site:.3e} (bounds {tol:.2e}, "
+              f"{SITE_FACTOR * tol:.2e})")
+        assert err <= tol and site <= SITE_FACTOR * tol
+    alone = host(ctx.sap(dev(etas[1])))
+    assert np.array_equal(alone, got[1])
+
+
+@pytest.mark.parametrize("product", TILE_PRODUCTS)
+def test_solve_tile(product, oracle):
+    """Five right-hand sides solved together with the tile forms: true residual
+    and solution against the oracle's solve of each."""
+    case = SMALL[2]
+    fs = np.stack([case.source(70 + k) for k in range(5)])
+    ctx = case.context()
+    ctx.set_sap(case.n_cycles, case.n_mr, "f16", product)
+    ctx.set_solver(16, 1e-10, 64)
+    x, info, status = ctx.solve(dev(fs))
+    assert status == 0
+    x = host(x)
+    for k in range(len(fs)):
+        x_or, st, steps, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, fs[k], n_cycles=case.n_cycles,
+                                         n_mr=case.n_mr, restart=16, tol=1e-12)
+        true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x[k]), fs[k])
+        err = rel(x[k], x_or)
+        print(f"{case} {product} rhs {k}: steps {info[k]['iters']} (oracle fp64 {steps}), true residual "
+              f"{true_res:.2e}, solution error {err:.2e}")
+        assert st == 0 and true_res <= 1e-10 and err <= 1e-8
+
+
+def test_tile_graph_batch_and_rejects():
+    """Graph replays of tile launches give the eager bits; a batch mixing a
+    tiled lattice with another gives each system's own result; shapes and
+    precisions without a tile kernel are refused."""
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[2]
+    ctx = case.context()
+    ctx.set_sap(case.n_cycles, case.n_mr, "f16", "mfma_f32")
+    etas = dev(np.stack([case.source(80 + k) for k in range(3)]))
+    eager = host(ctx.sap(etas))
+    ctx.set_schedule("graph")
+    for _ in range(3):
+        assert np.array_equal(host(ctx.sap(etas)), eager)
+        ctx.apply_D(etas[0].contiguous(), "f64")
+    ctx.set_schedule("sweeps")
+    other = SMALL[3].context("f32")
+    other.set_sap(case.n_cycles, 5, "f32")
+    fa, fb = dev(case.source(81)), dev(SMALL[3].source(82))
+    xs, infos, st = ddqcd.solve_batch([ctx, other, ctx], [fa, fb, fa])
+    assert st == ddqcd.OK
+    x1, _, _ = ctx.solve(fa)
+    assert np.array_equal(host(x1), host(xs[0])) and np.array_equal(host(x1), host(xs[2]))
+    for bad in ((SMALL[3], "f16"), (SMALL[2], "f32"), (SMALL[2], "f64")):
+        c = bad[0].context()
+        with pytest.raises(ddqcd.DDQCDError) as e:
+            c.set_sap(4, 5, bad[1], "mfma_f32")
+        assert e.value.status == ddqcd.ERR_GEOMETRY
