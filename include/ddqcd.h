@@ -168,6 +168,26 @@ int ddqcd_apply_D(ddqcd_t ctx, double *out, const double *in, int nrhs, int prec
  * in and out must not alias. */
 int ddqcd_sap(ddqcd_t ctx, double *out, const double *in, int nrhs, void *stream);
 
+/* out = M in for one right-hand side, as ddqcd_sap, without allocating any
+ * memory: for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  All work space
+ * (internal copies of in and out, the solution accumulator, block residuals,
+ * boundary terms, the launch arguments and the domain lists) is carved from
+ * one device array of the library, 128 MiB per device, which every device the
+ * library runs on holds until the process ends; ddqcd_load_gauge looks up its
+ * address on the context's device.  A lattice whose work space does not fit
+ * (about 940 bytes per site with 8x4x4x4 domains, more with smaller domains or
+ * the additive variant; 16^3x32 with 8x4x4x4 domains fits) returns
+ * DDQCD_ERR_NOMEM.  Every call on one device uses that same array: calls that
+ * overlap on one device (two streams, two host threads) race and give wrong
+ * results; calls ordered in one stream are safe, and nothing of an earlier
+ * call's contents is read.  Settings as for ddqcd_sap (ddqcd_set_sap,
+ * ddqcd_set_schwarz); the launches are issued one by one whatever
+ * ddqcd_set_schedule says.  The kernels and their order are those of
+ * ddqcd_sap with nrhs = 1, so the result is the same bit for bit.  in and out:
+ * device pointers, canonical layout, must not alias.  Asynchronous on stream. */
+int ddqcd_sap_noalloc(ddqcd_t ctx, double *out, const double *in, void *stream);
+
 /* Solves A x = b for nrhs right-hand sides with SAP-preconditioned FGCR.  If
  * x_is_guess, x holds the initial guess; else it starts from zero.  info
  * (optional) receives nrhs records.  Returns DDQCD_OK when every right-hand

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,7 +26,39 @@
 
 using namespace dd;
 
+// ---- device scratch of ddqcd_sap_noalloc ------------------------------------
+//
+// One copy of this array lives on every device the library runs on, for the
+// life of the process.  Host code never uses its name as an address: the
+// device address is looked up once per device (scratch_setup) and kept in
+// scratch_dev.
+constexpr size_t SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
 namespace {
+
+std::mutex scratch_mu;
+std::map<int, unsigned char *> scratch_dev;   // device -> address of its scratch
+
+// Looks up this device's scratch address (the device must be current).
+hipError_t scratch_setup(int device)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev.count(device)) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = (unsigned char *)p;
+    return hipSuccess;
+}
+
+unsigned char *scratch_for(int device)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    auto it = scratch_dev.find(device);
+    return it == scratch_dev.end() ? nullptr : it->second;
+}
 
 // work space of one right-hand side of a context
 struct Slot {
@@ -1034,6 +1067,7 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
     const size_t V = (size_t)g.V;
     if (c->device < 0) {
         HIPCHK(c, hipGetDevice(&c->device));
+        HIPCHK(c, scratch_setup(c->device));
         if ((e = alloc(c, &c->d_flag, sizeof(int)))) return e;
         if ((e = alloc(c, &c->U64, V * 4 * 9 * 16))) return e;
         if ((e = dev_alloc(c, &c->U32, V * 4 * 6 * 8))) return e;
@@ -1114,6 +1148,78 @@ int ddqcd_sap(ddqcd_t c, double *out, const double *in, int nrhs, void *stream)
     }
     if ((e = run_sap(sys, eta, o, std::vector<int>(nrhs, 1), s))) return e;
     for (int k = 0; k < nrhs; k++) HIPCHK(c, export_spinor(g, c->slots[k]->x, P64, out + (size_t)k * n * 2, s));
+    return DDQCD_OK;
+}
+
+int ddqcd_sap_noalloc(ddqcd_t c, double *out, const double *in, void *stream)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (!out || !in || out == in) return fail(c, DDQCD_ERR_ARG, "bad sap_noalloc arguments");
+    int e = check_ready(c, "sap_noalloc");
+    if (e) return e;
+    unsigned char *base = scratch_for(c->device);
+    if (!base) return fail(c, DDQCD_ERR_STATE, "no scratch address for this device");
+    hipStream_t s = (hipStream_t)stream;
+    const Geo &g = c->g;
+    const bool additive = c->schwarz == DDQCD_SCHWARZ_ADDITIVE;
+    // carve the scratch into 256-byte aligned pieces
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base + off;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const size_t nc = (size_t)ncomplex(g), half = (size_t)g.nd * 12 * g.Vh;
+    const size_t faces = (size_t)g.nd * sap_face_sites(g.b) * 6;
+    SapArgs *d_args = (SapArgs *)take(sizeof(SapArgs));
+    int2 *items = (int2 *)take(sizeof(int2) * g.nd);
+    double2 *eta = (double2 *)take(nc * 16), *res_out = (double2 *)take(nc * 16);
+    void *psi = take(nc * 16), *res = take(half * 16), *rho_tmp = take(half * 16), *face = take(faces * 16);
+    void *face_alt = additive ? take(faces * 16) : nullptr;
+    float *res_scale = (float *)take((size_t)g.nd * 4), *face_scale = (float *)take((size_t)g.nd * 4);
+    float *face_scale_alt = additive ? (float *)take((size_t)g.nd * 4) : nullptr;
+    if (off > SCRATCH_BYTES)
+        return fail(c, DDQCD_ERR_NOMEM, "sap_noalloc needs " + std::to_string(off) + " bytes of scratch for this "
+                                        "lattice; the limit is " + std::to_string(SCRATCH_BYTES));
+    SapArgs a{};
+    a.g = g;
+    a.n_mr = c->n_mr;
+    a.eta = eta;
+    a.out = res_out;
+    a.psi = psi;
+    a.res = res;
+    a.res_scale = res_scale;
+    a.face = face;
+    a.face_scale = face_scale;
+    a.face_alt = face_alt;
+    a.face_scale_alt = face_scale_alt;
+    a.rho_tmp = rho_tmp;
+    a.links = links_for(c, c->sap_prec);
+    a.cs = schur_for(c, c->sap_prec);
+    a.active = 1;
+    HIPCHK(c, import_spinor(g, in, eta, P64, s));
+    HIPCHK(c, sap_put_args(a, d_args, s));
+    HIPCHK(c, sap_schedule_items(g, sap_rhs_per_workgroup(c->product) > 1 ? 1 << 24 : 0, items, s));
+    const int shape = sap_shape_id(g.b), prec = c->sap_prec, half_nd = g.nd / 2;
+    for (int cyc = 0; cyc < c->n_cycles; cyc++) {
+        Visit v{};
+        v.first = cyc == 0;
+        v.last = cyc == c->n_cycles - 1;
+        v.res_out = !v.last;
+        if (additive) {   // one launch per cycle over all domains, alternating boundary buffers
+            v.faces_in = cyc > 0;
+            v.faces_out = !v.last;
+            v.flip = cyc & 1;
+            HIPCHK(c, sap_sweep_batch(d_args, items, g.nd, shape, prec, c->product, v, s));
+            continue;
+        }
+        for (int col = 0; col < 2; col++) {
+            v.faces_in = !(cyc == 0 && col == 0);
+            v.faces_out = !(v.last && col == 1);
+            HIPCHK(c, sap_sweep_batch(d_args, items + col * half_nd, half_nd, shape, prec, c->product, v, s));
+        }
+    }
+    HIPCHK(c, export_spinor(g, res_out, P64, out, s));
     return DDQCD_OK;
 }
 

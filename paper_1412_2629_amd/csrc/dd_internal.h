@@ -86,6 +86,12 @@ int sap_domains_per_workgroup(int shape, int prec, int product);
 // The compiled domain shapes: ids 0 .. sap_shape_count() - 1 and their extents.
 int sap_shape_count();
 void sap_shape_extents(int shape, int b[4]);
+// Work items of one system on the device: [0, nd/2) its black domains, then
+// its white domains, each in increasing domain number (the order a plan of
+// one system uses), with item.x = x.  items holds nd entries.
+hipError_t sap_schedule_items(const Geo &g, int x, int2 *items, hipStream_t s);
+// *dst = a on the device, in stream order (no host copy).
+hipError_t sap_put_args(const SapArgs &a, SapArgs *dst, hipStream_t s);
 // One colour of one half-sweep for a list of (system, domain) items; args and
 // items are device arrays.  All systems share one domain shape (shape id).
 hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, int product,

@@ -1784,6 +1784,37 @@ long sap_face_sites(const int b[4])
     return 2 * (Vd / b[0] + Vd / b[1] + Vd / b[2] + Vd / b[3]);
 }
 
+// item i < nd/2: the i-th black domain (item.x = x), item nd/2 + i: the i-th
+// white one, in increasing domain number.  The domain grid's x extent is even,
+// so domains 2i and 2i + 1 lie in one x row and have opposite colours: the
+// i-th domain of colour c is the one of that pair with colour c.
+__global__ void k_schedule_items(Geo g, int x, int2 *items)
+{
+    const int half = g.nd / 2;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nd) return;
+    const int c = i >= half, j = i - c * half;
+    const int d0 = 2 * j;
+    const int rest = d0 / g.n[0];
+    const int D1 = rest % g.n[1], D2 = (rest / g.n[1]) % g.n[2], D3 = rest / (g.n[1] * g.n[2]);
+    const int colour0 = (D1 + D2 + D3) & 1;   // colour of domain 2j (its x coordinate is even)
+    items[i] = make_int2(x, d0 + ((c + colour0) & 1));
+}
+
+__global__ void k_put_args(SapArgs a, SapArgs *dst) { *dst = a; }
+
+hipError_t sap_schedule_items(const Geo &g, int x, int2 *items, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_schedule_items, (g.nd + 255) / 256, 256, 0, s, g, x, items);
+    return hipGetLastError();
+}
+
+hipError_t sap_put_args(const SapArgs &a, SapArgs *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_put_args, 1, 1, 0, s, a, dst);
+    return hipGetLastError();
+}
+
 hipError_t sap_sweep_batch(const SapArgs *args, const int2 *items, int nitems, int shape, int prec, int product,
                            Visit v, hipStream_t s)
 {

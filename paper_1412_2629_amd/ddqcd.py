@@ -20,7 +20,7 @@ PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
 
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
            "ddqcd_set_solver", "ddqcd_load_gauge",
-           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
+           "ddqcd_apply_D", "ddqcd_sap", "ddqcd_sap_noalloc", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
            "ddqcd_last_error",
            "ddqcd_status_string"]
 
@@ -59,6 +59,7 @@ def lib():
         L.ddqcd_load_gauge.argtypes = [vp, vp, vp]
         L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
         L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
+        L.ddqcd_sap_noalloc.argtypes = [vp, vp, vp, vp]
         L.ddqcd_solve.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
         L.ddqcd_solve_batch.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(vp), ctypes.POINTER(vp), i,
                                         ctypes.POINTER(Info), vp]
@@ -165,6 +166,15 @@ class Context:
         import torch
         out = torch.empty_like(eta) if out is None else out
         self._check(lib().ddqcd_sap(self._h, _ptr(out, "out"), _ptr(eta, "in"), self._nrhs(eta), _stream()), "sap")
+        return out
+
+    def sap_noalloc(self, eta, out=None):
+        """out = M eta for one right-hand side through ddqcd_sap_noalloc (the
+        library allocates nothing; out is allocated here unless given)."""
+        import torch
+        assert eta.shape == (self.V, 4, 3), eta.shape
+        out = torch.empty_like(eta) if out is None else out
+        self._check(lib().ddqcd_sap_noalloc(self._h, _ptr(out, "out"), _ptr(eta, "in"), _stream()), "sap_noalloc")
         return out
 
     def solve_bicgstab(self, b, x0=None, max_iter=20000, check=True):
