@@ -59,11 +59,16 @@ def test_create_settings_and_state_errors():
     assert st == ddqcd.OK and h.value
     L = ddqcd.lib()
     try:
-        assert L.ddqcd_set_sap(h, 0, 5, 1) == ddqcd.ERR_ARG
-        assert L.ddqcd_set_sap(h, 16, 0, 1) == ddqcd.ERR_ARG
-        assert L.ddqcd_set_sap(h, 16, 5, 7) == ddqcd.ERR_ARG
-        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16) == ddqcd.OK
-        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP64) == ddqcd.OK
+        lane, mfma = ddqcd.PRODUCT["lane"], ddqcd.PRODUCT["mfma_f32"]
+        assert L.ddqcd_set_sap(h, 0, 5, 1, lane) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 0, 1, lane) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 5, 7, lane) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16, 9) == ddqcd.ERR_ARG
+        # the tile forms need FP16 storage (and 4^4 domains, which this context has)
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP32, mfma) == ddqcd.ERR_GEOMETRY
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16, mfma) == ddqcd.OK
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP16, lane) == ddqcd.OK
+        assert L.ddqcd_set_sap(h, 16, 5, ddqcd.FP64, lane) == ddqcd.OK
         assert L.ddqcd_set_schwarz(h, 2) == ddqcd.ERR_ARG
         assert L.ddqcd_set_schwarz(h, 1) == ddqcd.OK
         assert L.ddqcd_set_schwarz(h, 0) == ddqcd.OK
@@ -77,6 +82,7 @@ def test_create_settings_and_state_errors():
         # no gauge field loaded yet: rejected before any device work
         assert L.ddqcd_apply_D(h, dummy, dummy2, 1, 0, None) == ddqcd.ERR_STATE
         assert L.ddqcd_sap(h, dummy, dummy2, 1, None) == ddqcd.ERR_STATE
+        assert L.ddqcd_sap_noalloc(h, dummy, dummy2, None) == ddqcd.ERR_STATE
         assert L.ddqcd_solve(h, dummy, dummy2, 1, 0, None, None) == ddqcd.ERR_STATE
         assert b"load_gauge" in L.ddqcd_last_error(h)
         assert L.ddqcd_solve_bicgstab(h, dummy, dummy2, 0, 100, None, None) == ddqcd.ERR_STATE
