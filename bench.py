@@ -96,6 +96,16 @@ def build(name, schedule, tune=False, schwarz="multiplicative", domain=None, pro
         srcs = [inputs.point_source(w.lattice, 0, s, c) for s in range(4) for c in range(3)][:w.nrhs]
     else:
         srcs = [inputs.gaussian_source(w.lattice, w.source_seed)]
+    if tune and domain is None and product == "auto":
+        # the (domain shape, product form) this workload solves fastest with (untimed set-up)
+        b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).cuda()
+        dom, product, ms = ddqcd.tune_sap(w.lattice, w.kappa, w.csw, torch.from_numpy(U).cuda(), b, w.prec,
+                                          w.n_cycles, w.n_mr, w.restart, w.tol, 64, w.bc)
+        log(f"[bench] tuned: domain {dom}, products {product}" + (f" ({ms:.1f} ms)" if ms >= 0 else " (only fit)"))
+        w = dataclasses.replace(w, domain=dom)
+        del b
+    elif product == "auto":
+        product = "lane"
     return [System(w, U, srcs, schedule, schwarz, product)]
 
 
@@ -135,11 +145,13 @@ def main():
                     help="Schwarz method of the preconditioner (the workloads are defined with multiplicative)")
     ap.add_argument("--domain", default=None,
                     help="override the workload's domain shape, e.g. 4,4,4,4 (single-lattice workloads)")
-    ap.add_argument("--product", default="lane", choices=["lane", "tile", "mfma_f32", "mfma_bf16"],
+    ap.add_argument("--product", default="auto", choices=["auto", "lane", "tile", "mfma_f32", "mfma_bf16"],
                     help="block-solve product form: one right-hand side per workgroup, or tiles of four with the "
-                         "link products on VALU, FP32 MFMA or BF16-input MFMA (4^4 domains, FP16 storage)")
+                         "link products on VALU, FP32 MFMA or BF16-input MFMA (4^4 domains, FP16 storage); auto: "
+                         "tuned with the domain shape by ddqcd_tune_sap")
     ap.add_argument("--no-tune", action="store_true",
-                    help="uneven batch: keep the listed domain shapes instead of autotuning them per lattice")
+                    help="keep the listed domain shapes (and one right-hand side per workgroup) instead of autotuning "
+                         "them per lattice")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a known-size kernel for "
                          "calibrating profiler byte counters)")
@@ -243,7 +255,9 @@ def main():
         wl = (f"{w0.name}: lattice {w0.lattice}, kappa {w0.kappa}, c_sw {w0.csw}, eps {w0.eps}, "
               f"domains {w0.domain}, SAP {w0.n_cycles} cycles x {w0.n_mr} MR ({w0.prec}), "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, {len(systems[0].srcs)} right-hand side(s), "
-              f"schedule {args.schedule}, {args.schwarz} Schwarz, block-solve products {args.product}")
+              f"schedule {args.schedule}, {args.schwarz} Schwarz, block-solve products {systems[0].product}"
+              + (" (domain shape and products autotuned)" if not args.no_tune and not args.domain
+                 and args.product == "auto" else ""))
         batch = len(systems[0].srcs)
     out = {
         "metric": METRIC,

@@ -62,7 +62,12 @@ typedef enum {
     DDQCD_ERR_NONFINITE = 7      /* NaN or Inf in the input or in a residual */
 } ddqcd_status;
 
-typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2 } ddqcd_prec;
+/* Storage and arithmetic of the block solves and of ddqcd_apply_D: FP64; FP32;
+ * FP16 storage (links as two rows, clover, block residual and boundary terms;
+ * power-of-two scales per domain for the spinors) with FP32 arithmetic; BF16
+ * storage (the same fields, FP32's exponent range, so no scales; 8-bit
+ * significand) with FP32 arithmetic (Sec. III-B: reduced-precision storage). */
+typedef enum { DDQCD_FP64 = 0, DDQCD_FP32 = 1, DDQCD_FP16 = 2, DDQCD_BF16 = 3 } ddqcd_prec;
 
 typedef enum { DDQCD_SCHED_SWEEPS = 0, DDQCD_SCHED_QUEUE = 1, DDQCD_SCHED_GRAPH = 2 } ddqcd_schedule;
 typedef enum { DDQCD_SCHWARZ_MULTIPLICATIVE = 0, DDQCD_SCHWARZ_ADDITIVE = 1 } ddqcd_schwarz;
@@ -105,8 +110,8 @@ int ddqcd_destroy(ddqcd_t ctx);
  * half-spinors, FP32 inputs and accumulation), DDQCD_PRODUCT_MFMA_BF16 on
  * BF16-input matrix instructions with FP32 accumulation (link and half-spinor
  * rounded to BF16 for the product).  The tile forms need 4x4x4x4 domains and
- * DDQCD_FP16 storage; a solve or preconditioner call with nrhs right-hand sides
- * uses ceil(nrhs / 4) tiles. */
+ * DDQCD_FP16 or DDQCD_BF16 storage; a solve or preconditioner call with nrhs
+ * right-hand sides uses ceil(nrhs / 4) tiles. */
 typedef enum {
     DDQCD_PRODUCT_LANE = 0,
     DDQCD_PRODUCT_TILE_VALU = 1,
@@ -115,9 +120,9 @@ typedef enum {
 } ddqcd_product;
 
 /* Schwarz preconditioner settings: n_cycles = I_Schwarz >= 1, n_mr = I_domain
- * >= 1 (Sec. II-D), prec = storage/arithmetic of the block solves:
- * DDQCD_FP64, DDQCD_FP32, or DDQCD_FP16 (FP16 links, clover and spinors with
- * per-domain scales, FP32 arithmetic, FP32 solution accumulator); product = a
+ * >= 1 (Sec. II-D), prec = storage/arithmetic of the block solves, a
+ * ddqcd_prec (reduced storage with FP32 arithmetic and an FP32 solution
+ * accumulator); product = a
  * ddqcd_product.  Every precision is available with DDQCD_PRODUCT_LANE for
  * every domain shape ddqcd_create accepts, except FP64 on 6x6x2x4 domains.
  * DDQCD_ERR_GEOMETRY for a combination without a kernel, DDQCD_ERR_ARG for
@@ -237,7 +242,7 @@ int ddqcd_solve_bicgstab(ddqcd_t ctx, double *x, const double *b, int x_is_guess
  * canonical layout) and b solved (device pointer, canonical layout, one
  * right-hand side) twice with the given settings; the second solve is timed.
  * The fastest shape that converged is written to domain_out and its solve time
- * in milliseconds to ms_out (optional).  If only one shape fits, it is
+ * in milliseconds to ms_out (optional).  Products: DDQCD_PRODUCT_LANE.  If only one shape fits, it is
  * returned without timing and ms_out is set to -1.  Allocates and frees its
  * own device memory (one solution vector and the candidates' contexts, one at
  * a time).  Returns DDQCD_ERR_GEOMETRY if no compiled shape fits, otherwise
@@ -245,6 +250,21 @@ int ddqcd_solve_bicgstab(ddqcd_t ctx, double *x, const double *b, int x_is_guess
 int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
                       const double *b, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
                       int domain_out[4], double *ms_out, void *stream);
+
+/* ddqcd_tune_domain for nrhs right-hand sides solved together (b: nrhs
+ * spinor fields, canonical layout, one after the other) over the pairs (domain
+ * shape, product form): for every compiled shape that tiles the lattice and
+ * every ddqcd_product its kernels offer for prec (the tile forms only when
+ * nrhs >= 2: they take four right-hand sides per workgroup), a context is
+ * created, U loaded and the nrhs systems solved twice, the second solve timed;
+ * the fastest pair that converged is written to domain_out and product_out
+ * (optional), its time in milliseconds to ms_out (optional; -1 when only one
+ * pair fits and nothing was timed).  Allocates and frees its own device memory
+ * (nrhs solution vectors and the candidates' contexts, one at a time).  Errors
+ * as ddqcd_tune_domain. */
+int ddqcd_tune_sap(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
+                   const double *b, int nrhs, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
+                   int domain_out[4], int *product_out, double *ms_out, void *stream);
 
 /* Text of the last error on this context (never NULL; "" if none). */
 const char *ddqcd_last_error(ddqcd_t ctx);

@@ -120,11 +120,11 @@ struct ddqcd_ctx {
     // device memory (owned)
     int *d_flag = nullptr;
     double2 *U64 = nullptr;                // [d][mu][9][Vd]
-    void *U32 = nullptr, *U16 = nullptr;   // [d][mu][6][Vd]
+    void *U32 = nullptr, *U16 = nullptr, *UB16 = nullptr;   // [d][mu][6][Vd]
     double2 *C64 = nullptr;                // [d][36][Vd]
-    void *C32 = nullptr, *C16 = nullptr;
+    void *C32 = nullptr, *C16 = nullptr, *CB16 = nullptr;
     double2 *Cs64 = nullptr;               // C_e / C_o^-1
-    void *Cs32 = nullptr, *Cs16 = nullptr;
+    void *Cs32 = nullptr, *Cs16 = nullptr, *CsB16 = nullptr;
     void *t_lo_in = nullptr, *t_lo_out = nullptr;   // FP32/FP16 operands of apply_D
     hipStream_t capture = nullptr;   // private stream on which launch graphs are captured
     // reduction results of the systems of a solve led by this context, side by
@@ -182,9 +182,23 @@ int check_ready(ddqcd_t c, const char *what)
     return check_device(c);
 }
 
-const void *links_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->U64 : prec == DDQCD_FP32 ? c->U32 : c->U16; }
-const void *clover_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->C64 : prec == DDQCD_FP32 ? c->C32 : c->C16; }
-const void *schur_for(ddqcd_t c, int prec) { return prec == DDQCD_FP64 ? (void *)c->Cs64 : prec == DDQCD_FP32 ? c->Cs32 : c->Cs16; }
+// the copies of the links, clover term and C_e / C_o^-1 in one storage precision
+const void *links_for(ddqcd_t c, int prec)
+{
+    const void *f[4] = {c->U64, c->U32, c->U16, c->UB16};
+    return f[prec];
+}
+const void *clover_for(ddqcd_t c, int prec)
+{
+    const void *f[4] = {c->C64, c->C32, c->C16, c->CB16};
+    return f[prec];
+}
+const void *schur_for(ddqcd_t c, int prec)
+{
+    const void *f[4] = {c->Cs64, c->Cs32, c->Cs16, c->CsB16};
+    return f[prec];
+}
+bool valid_prec(int prec) { return prec >= DDQCD_FP64 && prec <= DDQCD_BF16; }
 
 // ---- per right-hand-side work space ----------------------------------------
 
@@ -1011,12 +1025,13 @@ int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec, int product)
 {
     if (!c) return DDQCD_ERR_ARG;
     if (n_cycles < 1 || n_mr < 1 || n_cycles > 1000 || n_mr > 1000) return fail(c, DDQCD_ERR_ARG, "bad SAP iteration counts");
-    if (prec != DDQCD_FP64 && prec != DDQCD_FP32 && prec != DDQCD_FP16) return fail(c, DDQCD_ERR_ARG, "bad precision");
+    if (!valid_prec(prec)) return fail(c, DDQCD_ERR_ARG, "bad precision");
     if (product < DDQCD_PRODUCT_LANE || product > DDQCD_PRODUCT_MFMA_BF16) return fail(c, DDQCD_ERR_ARG, "bad product form");
     if (!sap_prec_supported(c->g.b, prec))
         return fail(c, DDQCD_ERR_GEOMETRY, "no block-solve kernel for this domain shape and precision");
     if (!sap_product_supported(c->g.b, prec, product))
-        return fail(c, DDQCD_ERR_GEOMETRY, "the right-hand-side tile forms need 4x4x4x4 domains and FP16 storage");
+        return fail(c, DDQCD_ERR_GEOMETRY, "the right-hand-side tile forms need 4x4x4x4 domains and FP16 or BF16 "
+                                           "storage");
     c->n_cycles = n_cycles;
     c->n_mr = n_mr;
     c->sap_prec = prec;
@@ -1072,12 +1087,15 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
         if ((e = alloc(c, &c->U64, V * 4 * 9 * 16))) return e;
         if ((e = dev_alloc(c, &c->U32, V * 4 * 6 * 8))) return e;
         if ((e = dev_alloc(c, &c->U16, V * 4 * 6 * 4))) return e;
+        if ((e = dev_alloc(c, &c->UB16, V * 4 * 6 * 4))) return e;
         if ((e = alloc(c, &c->C64, V * 36 * 16))) return e;
         if ((e = dev_alloc(c, &c->C32, V * 36 * 8))) return e;
         if ((e = dev_alloc(c, &c->C16, V * 36 * 4))) return e;
+        if ((e = dev_alloc(c, &c->CB16, V * 36 * 4))) return e;
         if ((e = alloc(c, &c->Cs64, V * 36 * 16))) return e;
         if ((e = dev_alloc(c, &c->Cs32, V * 36 * 8))) return e;
         if ((e = dev_alloc(c, &c->Cs16, V * 36 * 4))) return e;
+        if ((e = dev_alloc(c, &c->CsB16, V * 36 * 4))) return e;
     }
     c->loaded = false;
     HIPCHK(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), s));
@@ -1089,12 +1107,15 @@ int ddqcd_load_gauge(ddqcd_t c, const double *U, void *stream)
     HIPCHK(c, import_gauge(g, U, c->U64, s));
     HIPCHK(c, compress_links(g, c->U64, c->U32, P32, s));
     HIPCHK(c, compress_links(g, c->U64, c->U16, P16, s));
+    HIPCHK(c, compress_links(g, c->U64, c->UB16, PB16, s));
     HIPCHK(c, clover_build(g, c->U64, c->kappa, c->csw, c->C64, s));
     HIPCHK(c, convert_pairs(c->C64, c->C32, (long)V * 36, P32, s));
     HIPCHK(c, convert_pairs(c->C64, c->C16, (long)V * 36, P16, s));
+    HIPCHK(c, convert_pairs(c->C64, c->CB16, (long)V * 36, PB16, s));
     HIPCHK(c, clover_schur(g, c->C64, c->Cs64, c->d_flag, s));
     HIPCHK(c, convert_pairs(c->Cs64, c->Cs32, (long)V * 36, P32, s));
     HIPCHK(c, convert_pairs(c->Cs64, c->Cs16, (long)V * 36, P16, s));
+    HIPCHK(c, convert_pairs(c->Cs64, c->CsB16, (long)V * 36, PB16, s));
     HIPCHK(c, hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (bad) return fail(c, DDQCD_ERR_ARG, "singular clover block on an odd site");
@@ -1106,7 +1127,7 @@ int ddqcd_apply_D(ddqcd_t c, double *out, const double *in, int nrhs, int prec, 
 {
     if (!c) return DDQCD_ERR_ARG;
     if (!out || !in || nrhs < 1 || out == in) return fail(c, DDQCD_ERR_ARG, "bad apply_D arguments");
-    if (prec != DDQCD_FP64 && prec != DDQCD_FP32 && prec != DDQCD_FP16) return fail(c, DDQCD_ERR_ARG, "bad precision");
+    if (!valid_prec(prec)) return fail(c, DDQCD_ERR_ARG, "bad precision");
     int e = check_ready(c, "apply_D");
     if (e || (e = ensure_slots(c, 1))) return e;
     hipStream_t s = (hipStream_t)stream;
@@ -1290,52 +1311,64 @@ int ddqcd_solve_bicgstab(ddqcd_t c, double *x, const double *b, int x_is_guess, 
     return st;
 }
 
-int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
-                      const double *b, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
-                      int domain_out[4], double *ms_out, void *stream)
+int ddqcd_tune_sap(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
+                   const double *b, int nrhs, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
+                   int domain_out[4], int *product_out, double *ms_out, void *stream)
 {
-    if (!lattice || !boundary || !U || !b || !domain_out) return DDQCD_ERR_ARG;
-    // the compiled shapes that tile this lattice
-    std::vector<std::vector<int>> cand;
+    if (!lattice || !boundary || !U || !b || !domain_out || nrhs < 1) return DDQCD_ERR_ARG;
+    // the compiled (shape, product) pairs that tile this lattice; the tile
+    // forms only for several right-hand sides
+    struct Cand {
+        int b[4], product;
+    };
+    std::vector<Cand> cand;
     for (int sh = 0; sh < sap_shape_count(); sh++) {
-        int bd[4];
-        sap_shape_extents(sh, bd);
-        bool ok = sap_prec_supported(bd, prec);
+        Cand cd;
+        sap_shape_extents(sh, cd.b);
+        bool ok = true;
         for (int m = 0; m < 4; m++) {
-            if (lattice[m] < 2 || lattice[m] % bd[m]) ok = false;
-            else if ((lattice[m] / bd[m]) % 2 || lattice[m] / bd[m] < 2) ok = false;
+            if (lattice[m] < 2 || lattice[m] % cd.b[m]) ok = false;
+            else if ((lattice[m] / cd.b[m]) % 2 || lattice[m] / cd.b[m] < 2) ok = false;
         }
-        if (ok) cand.push_back({bd[0], bd[1], bd[2], bd[3]});
+        if (!ok) continue;
+        for (int pr = DDQCD_PRODUCT_LANE; pr <= DDQCD_PRODUCT_MFMA_BF16; pr++) {
+            if (pr != DDQCD_PRODUCT_LANE && nrhs < 2) continue;
+            if (!sap_product_supported(cd.b, prec, pr)) continue;
+            cd.product = pr;
+            cand.push_back(cd);
+        }
     }
     if (cand.empty()) return DDQCD_ERR_GEOMETRY;
     if (cand.size() == 1) {   // nothing to choose: no timing
-        for (int m = 0; m < 4; m++) domain_out[m] = cand[0][m];
+        for (int m = 0; m < 4; m++) domain_out[m] = cand[0].b[m];
+        if (product_out) *product_out = cand[0].product;
         if (ms_out) *ms_out = -1;
         return DDQCD_OK;
     }
-    const size_t bytes = (size_t)lattice[0] * lattice[1] * lattice[2] * lattice[3] * 12 * 16;
+    const size_t bytes = (size_t)lattice[0] * lattice[1] * lattice[2] * lattice[3] * 12 * 16 * nrhs;
     double *x = nullptr;
     if (hipMalloc(&x, bytes) != hipSuccess) return DDQCD_ERR_NOMEM;
     double best = 0;
     int found = 0, last = DDQCD_ERR_GEOMETRY;
-    for (const std::vector<int> &bd : cand) {
+    for (const Cand &cd : cand) {
         ddqcd_t c = nullptr;
-        int st = ddqcd_create(lattice, bd.data(), kappa, c_sw, boundary, &c);
-        if (st == DDQCD_OK) st = ddqcd_set_sap(c, n_cycles, n_mr, prec, DDQCD_PRODUCT_LANE);
+        int st = ddqcd_create(lattice, cd.b, kappa, c_sw, boundary, &c);
+        if (st == DDQCD_OK) st = ddqcd_set_sap(c, n_cycles, n_mr, prec, cd.product);
         if (st == DDQCD_OK) st = ddqcd_set_solver(c, restart, tol, max_cycles);
         if (st == DDQCD_OK) st = ddqcd_load_gauge(c, U, stream);
-        if (st == DDQCD_OK) st = ddqcd_solve(c, x, b, 1, 0, nullptr, stream);   // first call builds the plans
+        if (st == DDQCD_OK) st = ddqcd_solve(c, x, b, nrhs, 0, nullptr, stream);   // first call builds the plans
         double ms = 0;
         if (st == DDQCD_OK) {
             const auto t0 = std::chrono::steady_clock::now();
-            st = ddqcd_solve(c, x, b, 1, 0, nullptr, stream);
+            st = ddqcd_solve(c, x, b, nrhs, 0, nullptr, stream);
             ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
         ddqcd_destroy(c);
         if (st == DDQCD_OK && (!found || ms < best)) {
             best = ms;
             found = 1;
-            for (int m = 0; m < 4; m++) domain_out[m] = bd[m];
+            for (int m = 0; m < 4; m++) domain_out[m] = cd.b[m];
+            if (product_out) *product_out = cd.product;
         } else if (st != DDQCD_OK) {
             last = st;
         }
@@ -1344,6 +1377,14 @@ int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const dou
     if (!found) return last;
     if (ms_out) *ms_out = best;
     return DDQCD_OK;
+}
+
+int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
+                      const double *b, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
+                      int domain_out[4], double *ms_out, void *stream)
+{
+    return ddqcd_tune_sap(lattice, kappa, c_sw, boundary, U, b, 1, prec, n_cycles, n_mr, restart, tol, max_cycles,
+                          domain_out, nullptr, ms_out, stream);
 }
 
 }  // extern "C"

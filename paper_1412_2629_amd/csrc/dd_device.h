@@ -22,11 +22,14 @@ namespace dd {
 
 typedef _Float16 half_t;
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16_t;
+typedef __bf16 bf162_t __attribute__((ext_vector_type(2)));
 
 template <typename S> struct vec2;
 template <> struct vec2<double> { typedef double2 type; };
 template <> struct vec2<float> { typedef float2 type; };
 template <> struct vec2<half_t> { typedef half2_t type; };
+template <> struct vec2<bf16_t> { typedef bf162_t type; };
 template <typename S> using v2 = typename vec2<S>::type;
 
 template <typename T> struct cx {

@@ -6,7 +6,7 @@
 
 namespace dd {
 
-enum { P64 = 0, P32 = 1, P16 = 2 };
+enum { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };   // FP64, FP32, FP16, BF16 storage
 
 // Canonical FP64 spinor [V][12] complex <-> internal layout in precision prec.
 hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int prec, hipStream_t s);

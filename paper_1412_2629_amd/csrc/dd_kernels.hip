@@ -45,7 +45,8 @@ hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int 
     unsigned nb = nblocks(g.V, 256);
     if (prec == P64) hipLaunchKernelGGL(k_import_spinor<double>, nb, 256, 0, s, g, (const double2 *)canon, (double2 *)internal);
     else if (prec == P32) hipLaunchKernelGGL(k_import_spinor<float>, nb, 256, 0, s, g, (const double2 *)canon, (float2 *)internal);
-    else hipLaunchKernelGGL(k_import_spinor<half_t>, nb, 256, 0, s, g, (const double2 *)canon, (half2_t *)internal);
+    else if (prec == P16) hipLaunchKernelGGL(k_import_spinor<half_t>, nb, 256, 0, s, g, (const double2 *)canon, (half2_t *)internal);
+    else hipLaunchKernelGGL(k_import_spinor<bf16_t>, nb, 256, 0, s, g, (const double2 *)canon, (bf162_t *)internal);
     return hipGetLastError();
 }
 
@@ -54,7 +55,8 @@ hipError_t export_spinor(const Geo &g, const void *internal, int prec, double *c
     unsigned nb = nblocks(g.V, 256);
     if (prec == P64) hipLaunchKernelGGL(k_export_spinor<double>, nb, 256, 0, s, g, (const double2 *)internal, (double2 *)canon);
     else if (prec == P32) hipLaunchKernelGGL(k_export_spinor<float>, nb, 256, 0, s, g, (const float2 *)internal, (double2 *)canon);
-    else hipLaunchKernelGGL(k_export_spinor<half_t>, nb, 256, 0, s, g, (const half2_t *)internal, (double2 *)canon);
+    else if (prec == P16) hipLaunchKernelGGL(k_export_spinor<half_t>, nb, 256, 0, s, g, (const half2_t *)internal, (double2 *)canon);
+    else hipLaunchKernelGGL(k_export_spinor<bf16_t>, nb, 256, 0, s, g, (const bf162_t *)internal, (double2 *)canon);
     return hipGetLastError();
 }
 
@@ -92,7 +94,8 @@ hipError_t compress_links(const Geo &g, const double2 *U64, void *out, int prec,
 {
     unsigned nb = nblocks(g.V, 256);
     if (prec == P32) hipLaunchKernelGGL(k_compress_links<float>, nb, 256, 0, s, g, U64, (float2 *)out);
-    else hipLaunchKernelGGL(k_compress_links<half_t>, nb, 256, 0, s, g, U64, (half2_t *)out);
+    else if (prec == P16) hipLaunchKernelGGL(k_compress_links<half_t>, nb, 256, 0, s, g, U64, (half2_t *)out);
+    else hipLaunchKernelGGL(k_compress_links<bf16_t>, nb, 256, 0, s, g, U64, (bf162_t *)out);
     return hipGetLastError();
 }
 
@@ -106,7 +109,8 @@ hipError_t convert_pairs(const double2 *in, void *out, long n, int prec, hipStre
 {
     unsigned nb = nblocks(n, 256);
     if (prec == P32) hipLaunchKernelGGL(k_convert_pairs<float>, nb, 256, 0, s, in, (float2 *)out, n);
-    else hipLaunchKernelGGL(k_convert_pairs<half_t>, nb, 256, 0, s, in, (half2_t *)out, n);
+    else if (prec == P16) hipLaunchKernelGGL(k_convert_pairs<half_t>, nb, 256, 0, s, in, (half2_t *)out, n);
+    else hipLaunchKernelGGL(k_convert_pairs<bf16_t>, nb, 256, 0, s, in, (bf162_t *)out, n);
     return hipGetLastError();
 }
 
@@ -409,9 +413,12 @@ hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, c
     else if (prec == P32)
         hipLaunchKernelGGL((k_apply_A<float, float, float, float, 6>), nb, 256, 0, s, g, (const float2 *)in,
                            (float2 *)out, (const float2 *)links, (const float2 *)clov);
-    else
+    else if (prec == P16)
         hipLaunchKernelGGL((k_apply_A<float, half_t, half_t, half_t, 6>), nb, 256, 0, s, g, (const half2_t *)in,
                            (half2_t *)out, (const half2_t *)links, (const half2_t *)clov);
+    else
+        hipLaunchKernelGGL((k_apply_A<float, bf16_t, bf16_t, bf16_t, 6>), nb, 256, 0, s, g, (const bf162_t *)in,
+                           (bf162_t *)out, (const bf162_t *)links, (const bf162_t *)clov);
     return hipGetLastError();
 }
 

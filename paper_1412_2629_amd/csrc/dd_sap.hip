@@ -1696,8 +1696,22 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
     if (product != PRODUCT_LANE) {
         // a tile of right-hand sides per workgroup: 4^4 domains, FP16 storage
         if constexpr (std::is_same<Sh, Shape<4, 4, 4, 4>>::value) {
-            if (prec != P16) return hipErrorInvalidValue;
             constexpr int NT = Sh::VH * RT;
+            if (prec == PB16) {
+                switch (product) {
+                    case PRODUCT_TILE_VALU:
+                        return launch_bounded(k_sap_tile<Sh, PROD_VALU, bf16_t, bf16_t, false>, nitems, NT, s, args,
+                                              items, v);
+                    case PRODUCT_TILE_MFMA_F32:
+                        return launch_bounded(k_sap_tile<Sh, PROD_MFMA_F32, bf16_t, bf16_t, false>, nitems, NT, s, args,
+                                              items, v);
+                    case PRODUCT_TILE_MFMA_BF16:
+                        return launch_bounded(k_sap_tile<Sh, PROD_MFMA_BF16, bf16_t, bf16_t, false>, nitems, NT, s,
+                                              args, items, v);
+                    default: return hipErrorInvalidValue;
+                }
+            }
+            if (prec != P16) return hipErrorInvalidValue;
             switch (product) {
                 case PRODUCT_TILE_VALU:
                     return launch_bounded(k_sap_tile<Sh, PROD_VALU, half_t, half_t, true>, nitems, NT, s, args, items, v);
@@ -1729,8 +1743,11 @@ static hipError_t launch_batch(const SapArgs *args, const int2 *items, int nitem
         if (prec == P32)
             return launch_bounded(k_sap_lds<Sh, NDW, float, float, float, float, 6, 6, false, true, true>, nitems / NDW,
                                   NT, s, args, items, v);
-        else
+        else if (prec == P16)
             return launch_bounded(k_sap_lds<Sh, NDW, float, half_t, float, half_t, 6, 9, true, true, true>,
+                                  nitems / NDW, NT, s, args, items, v);
+        else
+            return launch_bounded(k_sap_lds<Sh, NDW, float, bf16_t, float, bf16_t, 6, 9, false, true, true>,
                                   nitems / NDW, NT, s, args, items, v);
     }
 }
@@ -1746,7 +1763,7 @@ bool sap_product_supported(const int b[4], int prec, int product)
 {
     if (product == PRODUCT_LANE) return sap_prec_supported(b, prec);
     if (product < PRODUCT_TILE_VALU || product > PRODUCT_TILE_MFMA_BF16) return false;
-    return sap_shape_id(b) == 1 && prec == P16;
+    return sap_shape_id(b) == 1 && (prec == P16 || prec == PB16);
 }
 
 int sap_shape_id(const int b[4])
@@ -1773,7 +1790,7 @@ bool sap_shape_supported(const int b[4]) { return sap_shape_id(b) >= 0; }
 bool sap_prec_supported(const int b[4], int prec)
 {
     const int id = sap_shape_id(b);
-    if (id < 0 || prec < P64 || prec > P16) return false;
+    if (id < 0 || prec < P64 || prec > PB16) return false;
     const int vd = b[0] * b[1] * b[2] * b[3];
     return prec != P64 || vd == 16 || vd % 64 == 0;
 }

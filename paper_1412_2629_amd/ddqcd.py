@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libddqcd.so")
 
 OK, ERR_ARG, ERR_GEOMETRY, ERR_STATE, ERR_DEVICE, ERR_NOMEM, ERR_NOT_CONVERGED, ERR_NONFINITE = range(8)
-FP64, FP32, FP16 = 0, 1, 2
-PREC = {"f64": FP64, "f32": FP32, "f16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PREC = {"f64": FP64, "f32": FP32, "f16": FP16, "bf16": BF16, FP64: FP64, FP32: FP32, FP16: FP16, BF16: BF16}
 
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
@@ -21,6 +21,7 @@ PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
 EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
            "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_sap_noalloc", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
+           "ddqcd_tune_sap",
            "ddqcd_last_error",
            "ddqcd_status_string"]
 
@@ -66,6 +67,8 @@ def lib():
         L.ddqcd_solve_bicgstab.argtypes = [vp, vp, vp, i, i, ctypes.POINTER(Info), vp]
         L.ddqcd_tune_domain.argtypes = [ctypes.POINTER(i), d, d, ctypes.POINTER(d), vp, vp, i, i, i, i, d, i,
                                         ctypes.POINTER(i), ctypes.POINTER(d), vp]
+        L.ddqcd_tune_sap.argtypes = [ctypes.POINTER(i), d, d, ctypes.POINTER(d), vp, vp, i, i, i, i, i, d, i,
+                                     ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(d), vp]
         L.ddqcd_last_error.argtypes = [vp]
         L.ddqcd_last_error.restype = ctypes.c_char_p
         L.ddqcd_status_string.argtypes = [i]
@@ -236,3 +239,24 @@ def tune_domain(lattice, kappa, csw, U, b, prec="f16", n_cycles=16, n_mr=5, rest
     if st != OK:
         raise DDQCDError(st, f"tune_domain({tuple(lattice)}): {status_string(st)}")
     return tuple(dom), ms.value
+
+
+def tune_sap(lattice, kappa, csw, U, b, prec="f16", n_cycles=16, n_mr=5, restart=16, tol=1e-10, max_cycles=64,
+             boundary=(1.0, 1.0, 1.0, -1.0)):
+    """The fastest (domain shape, product form) for solving the right-hand
+    sides b ((V, 4, 3) or (nrhs, V, 4, 3)) together on this lattice and gauge
+    field (ddqcd_tune_sap).  Returns (domain, product name, ms); ms is -1 when
+    only one pair fits and nothing was timed."""
+    V = int(lattice[0]) * int(lattice[1]) * int(lattice[2]) * int(lattice[3])
+    nrhs = 1 if tuple(b.shape) == (V, 4, 3) else b.shape[0]
+    dom = (ctypes.c_int * 4)()
+    prod = ctypes.c_int()
+    ms = ctypes.c_double()
+    st = lib().ddqcd_tune_sap((ctypes.c_int * 4)(*[int(v) for v in lattice]), ctypes.c_double(kappa),
+                              ctypes.c_double(csw), (ctypes.c_double * 4)(*[float(v) for v in boundary]),
+                              _ptr(U, "U"), _ptr(b, "b"), nrhs, PREC[prec], n_cycles, n_mr, restart,
+                              ctypes.c_double(tol), max_cycles, dom, ctypes.byref(prod), ctypes.byref(ms), _stream())
+    if st != OK:
+        raise DDQCDError(st, f"tune_sap({tuple(lattice)}): {status_string(st)}")
+    name = {v: k for k, v in PRODUCT.items()}[prod.value]
+    return tuple(dom), name, ms.value

@@ -19,7 +19,7 @@ import numpy as np
 import pytest
 
 from paper_1412_2629_amd import configs, inputs
-from tests.gpu_cases import BC, SAP_TOL, SITE_FACTOR, WIDE, dev, fp64_sap, host, rel, site_err
+from tests.gpu_cases import A_TOL, BC, SAP_TOL, SITE_FACTOR, WIDE, dev, fp64_sap, host, rel, site_err
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_refs")
 SOL_TOL = 1e-8   # solution against the oracle's solution (oracle solved to 1e-12)
@@ -43,7 +43,6 @@ def check_against_ref(key, x):
 
 pytestmark = pytest.mark.gpu
 
-A_TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -99,7 +98,7 @@ def test_apply_D_sampled(name, oracle):
     sites = sample_sites(w)
     want = oracle.apply_A_sites(w.lattice, w.bc, U, w.kappa, w.csw, f, sites)
     fd = dev(f)
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f64", "f32", "f16", "bf16"):
         got = host(ctx.apply_D(fd, prec))[sites]
         err = rel(got, want)
         print(f"{name} {prec}: operator error on {len(sites)} sampled sites {err:.3e}")
@@ -125,7 +124,7 @@ def test_sap_wide(case, oracle):
     eta = case.source(25)
     want = oracle.sap(case.L, case.b, BC, case.U, case.C, case.Ci, case.n_cycles, case.n_mr, eta)
     ctx = case.context()
-    for prec in ("f64", "f32", "f16"):
+    for prec in ("f64", "f32", "f16", "bf16"):
         if prec == "f64" and not fp64_sap(case):
             continue
         ctx.set_sap(case.n_cycles, case.n_mr, prec)

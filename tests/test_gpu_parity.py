@@ -10,12 +10,11 @@ Tolerances (normwise relative errors):
 import numpy as np
 import pytest
 
-from tests.gpu_cases import (BC, NO_FP64_SAP, PRODUCT_TOL, SAP_TOL, SITE_FACTOR, SMALL, WIDE, Case, dev, fp64_sap, host,
+from tests.gpu_cases import (A_TOL, BC, NO_FP64_SAP, PRODUCT_TOL, SAP_TOL, SITE_FACTOR, SMALL, WIDE, Case, dev, fp64_sap, host,
                              rel, site_err)
 
 pytestmark = pytest.mark.gpu
 
-A_TOL = {"f64": 1e-13, "f32": 1e-6, "f16": 5e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,7 +27,7 @@ def _gpu():
 
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
 def test_apply_D(case, prec, oracle):
     psi = case.source()
     want = oracle.apply_A(case.L, BC, case.U, case.C, psi)
@@ -74,7 +73,7 @@ QUEUE_SKIP = "work-queue schedule not built (stalled on the device, cause not es
 
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
-@pytest.mark.parametrize("prec", ["f32", "f16"])
+@pytest.mark.parametrize("prec", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("sched", ["sweeps", "queue"])
 def test_sap_low_precision(case, prec, sched, oracle):
     if sched == "queue":
@@ -116,7 +115,7 @@ def test_sap_homogeneous(case):
 
 
 @pytest.mark.parametrize("case", SMALL, ids=repr)
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
 def test_solve(case, prec, oracle):
     if prec == "f64" and not fp64_sap(case):
         pytest.skip(NO_FP64_SAP)
@@ -319,34 +318,37 @@ def tile_reference(case, oracle, n):
     return _tile_refs[case.name]
 
 
+TILE_FORMS = [("f16", "tile"), ("f16", "mfma_f32"), ("f16", "mfma_bf16"), ("bf16", "tile"), ("bf16", "mfma_bf16")]
+
+
 @pytest.mark.parametrize("case", [SMALL[2], WIDE[1]], ids=repr)
-@pytest.mark.parametrize("product", TILE_PRODUCTS)
-def test_sap_tile(case, product, oracle):
+@pytest.mark.parametrize("prec,product", TILE_FORMS)
+def test_sap_tile(case, prec, product, oracle):
     """Five right-hand sides (a full tile and a tile of one) against the
     oracle's SAP of each; a right-hand side solved alone (a tile of one) gives
     the bits it gets inside a full tile."""
     etas, want = tile_reference(case, oracle, 5)
     ctx = case.context()
-    ctx.set_sap(case.n_cycles, case.n_mr, "f16", product)
+    ctx.set_sap(case.n_cycles, case.n_mr, prec, product)
     got = host(ctx.sap(dev(etas)))
-    tol = PRODUCT_TOL[product]
+    tol = max(PRODUCT_TOL[product], SAP_TOL[prec])
     for k in range(len(etas)):
         err, site = site_err(got[k], want[k])
-        print(f"{case} {product} rhs {k}: error {err:.3e}, largest site error {site:.3e} (bounds {tol:.2e}, "
+        print(f"{case} {prec} {product} rhs {k}: error {err:.3e}, largest site error {site:.3e} (bounds {tol:.2e}, "
               f"{SITE_FACTOR * tol:.2e})")
         assert err <= tol and site <= SITE_FACTOR * tol
     alone = host(ctx.sap(dev(etas[1])))
     assert np.array_equal(alone, got[1])
 
 
-@pytest.mark.parametrize("product", TILE_PRODUCTS)
-def test_solve_tile(product, oracle):
+@pytest.mark.parametrize("prec,product", TILE_FORMS)
+def test_solve_tile(prec, product, oracle):
     """Five right-hand sides solved together with the tile forms: true residual
     and solution against the oracle's solve of each."""
     case = SMALL[2]
     fs = np.stack([case.source(70 + k) for k in range(5)])
     ctx = case.context()
-    ctx.set_sap(case.n_cycles, case.n_mr, "f16", product)
+    ctx.set_sap(case.n_cycles, case.n_mr, prec, product)
     ctx.set_solver(16, 1e-10, 64)
     x, info, status = ctx.solve(dev(fs))
     assert status == 0
@@ -383,7 +385,7 @@ def test_tile_graph_batch_and_rejects():
     assert st == ddqcd.OK
     x1, _, _ = ctx.solve(fa)
     assert np.array_equal(host(x1), host(xs[0])) and np.array_equal(host(x1), host(xs[2]))
-    for bad in ((SMALL[3], "f16"), (SMALL[2], "f32"), (SMALL[2], "f64")):
+    for bad in ((SMALL[3], "f16"), (SMALL[3], "bf16"), (SMALL[2], "f32"), (SMALL[2], "f64")):
         c = bad[0].context()
         with pytest.raises(ddqcd.DDQCDError) as e:
             c.set_sap(4, 5, bad[1], "mfma_f32")
