@@ -27,9 +27,11 @@
  *   spinor field    double[nrhs][V][4][3][2] psi(x)[spin][colour]
  * Pointers must be 16-byte aligned device memory of the current device.
  *
- * Ownership: the caller owns every pointer it passes.  The library owns the
- * device memory it allocates for a context (internal copies of the links,
- * clover terms, solver work vectors) and frees it in ddqcd_destroy.
+ * Ownership: the caller owns every pointer it passes.  The device memory of a
+ * context (internal copies of the links and clover terms, solver work
+ * vectors, launch plans) is either allocated by the library and freed in
+ * ddqcd_destroy, or carved from a workspace the caller hands over with
+ * ddqcd_set_workspace (the caller frees it after ddqcd_destroy).
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  apply_D
  * and sap are asynchronous on that stream; load_gauge and solve return
@@ -150,6 +152,30 @@ int ddqcd_set_schedule(ddqcd_t ctx, int schedule);
  * (twice the block solves in flight, no colouring).  Applies to ddqcd_sap and
  * ddqcd_solve; ddqcd_solve_batch requires it to be equal on all contexts. */
 int ddqcd_set_schwarz(ddqcd_t ctx, int kind);
+
+/* Device memory of a context supplied by the caller (for instance one torch
+ * allocation).  ddqcd_workspace_size writes to *bytes what the context needs to
+ * solve nrhs >= 1 right-hand sides at once (or apply the preconditioner or
+ * operator to them) with its current restart length: the copies of links,
+ * clover term and C_e / C_o^-1 in every precision; per right-hand side the
+ * work slot (solution accumulator, block residual, boundary terms of both
+ * Schwarz variants, FP64 vectors, reduction buffers, the FGCR basis of 2 x
+ * max(restart, 5) vectors); the apply_D operands; the reduction area; and a
+ * region for launch plans.  ddqcd_set_workspace hands the context dev_ptr
+ * (device memory of the device ddqcd_load_gauge will run on, 256-byte
+ * aligned, at least ddqcd_workspace_size(ctx, 1) bytes), before
+ * ddqcd_load_gauge and once per context: from then on every device array of
+ * the context is carved from it and the context calls no hipMalloc (the
+ * ddqcd_tune_* calls make contexts of their own).  The workspace serves the
+ * largest nrhs whose size fits; a call that needs more (more right-hand sides,
+ * a longer restart set afterwards, a ddqcd_solve_batch led by this context
+ * with more than max(nrhs, 64) systems) returns DDQCD_ERR_NOMEM.  The caller
+ * keeps the memory alive and unused by anything else until ddqcd_destroy,
+ * which does not free it.  Errors: DDQCD_ERR_ARG (null or misaligned pointer),
+ * DDQCD_ERR_NOMEM (smaller than one right-hand side needs), DDQCD_ERR_STATE
+ * (the context already holds device memory or a workspace). */
+int ddqcd_workspace_size(ddqcd_t ctx, int nrhs, size_t *bytes);
+int ddqcd_set_workspace(ddqcd_t ctx, void *dev_ptr, size_t bytes);
 
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the
  * true relative residual |b - A x|/|b| (Sec. IV-C1), max_cycles >= 1. */

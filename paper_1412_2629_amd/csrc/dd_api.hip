@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -90,9 +91,11 @@ struct Plan {
     std::vector<SapArgs> h_args;
     hipGraphExec_t graph = nullptr;   // the launches of one preconditioner call
     int graph_cycles = -1;
+    bool in_workspace = false;        // device arrays carved from the caller's workspace
     ~Plan()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
+        if (in_workspace) return;
         (void)hipFree(d_args);
         for (Group &G : groups)
             for (int c = 0; c < 3; c++) (void)hipFree(G.items[c]);
@@ -134,6 +137,14 @@ struct ddqcd_ctx {
     std::vector<std::unique_ptr<Slot>> slots;
     std::map<std::string, std::unique_ptr<Plan>> plans;   // batch plans led by this context
     std::vector<void *> owned;
+    // caller-owned workspace (ddqcd_set_workspace): every device array of the
+    // context is carved from it (bump allocation, 256-byte aligned) instead of
+    // hipMalloc; the plans live in a region at its top that is reset when full
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
+    unsigned char *ws_plan = nullptr;
+    size_t ws_plan_bytes = 0, ws_plan_used = 0;
+    int ws_nrhs = 0;
 };
 
 namespace {
@@ -154,8 +165,21 @@ int fail(ddqcd_t c, int code, const std::string &msg)
 
 long ncomplex(const Geo &g) { return g.V * 12; }
 
+size_t aligned(size_t bytes) { return (bytes + 255) / 256 * 256; }
+
 int dev_alloc(ddqcd_t c, void **p, size_t bytes)
 {
+    if (c->ws) {
+        const size_t need = aligned(bytes);
+        if (c->ws_used + need > c->ws_bytes - c->ws_plan_bytes) {
+            *p = nullptr;
+            return fail(c, DDQCD_ERR_NOMEM, "the workspace is too small: " + std::to_string(need) +
+                                                " more bytes needed (ddqcd_workspace_size)");
+        }
+        *p = c->ws + c->ws_used;
+        c->ws_used += need;
+        return DDQCD_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -166,6 +190,18 @@ int dev_alloc(ddqcd_t c, void **p, size_t bytes)
 }
 
 template <typename P> int alloc(ddqcd_t c, P **p, size_t bytes) { return dev_alloc(c, (void **)p, bytes); }
+
+// device array of a plan: hipMalloc, or carved from the workspace's plan
+// region (false when the region is full)
+bool plan_alloc(ddqcd_t lead, void **p, size_t bytes)
+{
+    if (!lead->ws) return hipMalloc(p, bytes) == hipSuccess;
+    const size_t need = aligned(bytes);
+    if (lead->ws_plan_used + need > lead->ws_plan_bytes) return false;
+    *p = lead->ws_plan + lead->ws_plan_used;
+    lead->ws_plan_used += need;
+    return true;
+}
 
 int check_device(ddqcd_t c)
 {
@@ -226,9 +262,10 @@ int ensure_slots(ddqcd_t c, int n)
     return DDQCD_OK;
 }
 
+// FGCR's z and w columns (at least 5: the BiCGstab work vectors)
 int ensure_basis(ddqcd_t c, Slot &sl, int columns = 0)
 {
-    const int want = std::max(columns, c->restart);
+    const int want = std::max(std::max(columns, c->restart), 5);
     if (sl.zw_restart >= want) return DDQCD_OK;
     const size_t nc = (size_t)ncomplex(c->g);
     int e;
@@ -261,6 +298,8 @@ std::string plan_key(const std::vector<Sys> &sys)
     return k;
 }
 
+int build_plan_once(const std::vector<Sys> &sys, const std::string &key, Plan *&out);
+
 int build_plan(const std::vector<Sys> &sys, Plan *&out)
 {
     ddqcd_t lead = sys[0].c;
@@ -273,9 +312,26 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
     if (lead->plans.size() >= MAX_PLANS) {
         HIPCHK(lead, hipDeviceSynchronize());   // no launch may still read an old plan
         lead->plans.clear();
+        lead->ws_plan_used = 0;
     }
+    int e = build_plan_once(sys, key, out);
+    if (e == DDQCD_ERR_NOMEM && lead->ws && !lead->plans.empty()) {
+        // the workspace's plan region is full: drop the cached plans and retry
+        HIPCHK(lead, hipDeviceSynchronize());
+        lead->plans.clear();
+        lead->ws_plan_used = 0;
+        e = build_plan_once(sys, key, out);
+    }
+    return e;
+}
+
+int build_plan_once(const std::vector<Sys> &sys, const std::string &key, Plan *&out)
+{
+    ddqcd_t lead = sys[0].c;
     auto plan = std::make_unique<Plan>();
-    HIPCHK(lead, hipMalloc(&plan->d_args, sizeof(SapArgs) * sys.size()));
+    plan->in_workspace = lead->ws != nullptr;
+    if (!plan_alloc(lead, (void **)&plan->d_args, sizeof(SapArgs) * sys.size()))
+        return fail(lead, DDQCD_ERR_NOMEM, "no device memory for a launch plan (workspace plan region full)");
     plan->h_args.resize(sys.size());
     // group the systems by (domain shape, precision, product form)
     std::vector<std::array<int, 3>> gk;
@@ -345,7 +401,8 @@ int build_plan(const std::vector<Sys> &sys, Plan *&out)
                     for (int q = 0; q < ndw; q++) items[(j * N_XCD + ln) * ndw + q] = lane[ln][j][q];
             while (!items.empty() && items[items.size() - ndw].x < 0) items.resize(items.size() - ndw);
             G.nitems[col] = (int)items.size();
-            HIPCHK(lead, hipMalloc(&G.items[col], sizeof(int2) * std::max<size_t>(1, items.size())));
+            if (!plan_alloc(lead, (void **)&G.items[col], sizeof(int2) * std::max<size_t>(1, items.size())))
+                return fail(lead, DDQCD_ERR_NOMEM, "no device memory for a launch plan (workspace plan region full)");
             HIPCHK(lead, hipMemcpy(G.items[col], items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
         }
     }
@@ -565,6 +622,12 @@ struct ResultArea {
     int bind()
     {
         const int ns = (int)sys.size();
+        if (lead->res_cap < ns && lead->ws)
+            return fail(lead, DDQCD_ERR_NOMEM, "more systems than the workspace's reduction area holds (" +
+                                                   std::to_string(lead->res_cap) + ")");
+        if (!lead->res_host && lead->res_cap > 0)   // pinned host copy of a workspace's reduction area
+            HIPCHK(lead, hipHostMalloc((void **)&lead->res_host, sizeof(double2) * 32 * lead->res_cap,
+                                       hipHostMallocDefault));
         if (lead->res_cap < ns) {
             int e;
             if ((e = alloc(lead, &lead->res_dev, sizeof(double2) * 32 * ns))) return e;
@@ -943,6 +1006,39 @@ int bicgstab(ddqcd_t c, Slot &sl, bool guess, int max_iter, ddqcd_info &info, hi
 
 bool is_pm1(double v) { return v == 1.0 || v == -1.0; }
 
+// ---- workspace layout ---------------------------------------------------------
+// The sum of every device array the context allocates for nrhs right-hand
+// sides (each rounded up to 256 bytes), in three parts: the reduction area at
+// the bottom, the arrays of load_gauge, the work slots and the apply_D
+// temporaries above it, and the plan region at the top.
+size_t ws_result_bytes(int nrhs) { return aligned(sizeof(double2) * 32 * std::max(nrhs, 64)); }
+
+size_t ws_plan_bytes(const Geo &g, int nrhs)
+{
+    const size_t per_plan =
+        aligned(sizeof(SapArgs) * nrhs) + 3 * aligned(sizeof(int2) * ((size_t)nrhs * g.nd + 64));
+    return (size_t)(nrhs + 3) * per_plan;
+}
+
+size_t ws_main_bytes(ddqcd_t c, int nrhs)
+{
+    const Geo &g = c->g;
+    const size_t V = (size_t)g.V, nc = V * 12, half = (size_t)g.nd * 12 * g.Vh;
+    const size_t faces = (size_t)g.nd * sap_face_sites(g.b) * 6;
+    size_t gauge = aligned(sizeof(int)) + aligned(V * 4 * 9 * 16) + aligned(V * 4 * 6 * 8) + 2 * aligned(V * 4 * 6 * 4);
+    gauge += 2 * (aligned(V * 36 * 16) + aligned(V * 36 * 8) + 2 * aligned(V * 36 * 4));   // clover, C_e / C_o^-1
+    size_t slot = 4 * aligned(nc * 16) + 2 * aligned(half * 16) + aligned(faces * 16) + 2 * aligned((size_t)g.nd * 4);
+    slot += aligned(sizeof(double2) * BLAS_NBLK * 32) + 2 * aligned(sizeof(double2) * 32);
+    slot += 2 * aligned(nc * 16 * std::max(c->restart, 5));                 // FGCR basis
+    slot += aligned(faces * 16) + aligned((size_t)g.nd * 4);                 // additive Schwarz
+    return gauge + (size_t)nrhs * slot + 2 * aligned(nc * 8);               // + apply_D operands
+}
+
+size_t ws_total_bytes(ddqcd_t c, int nrhs)
+{
+    return ws_result_bytes(nrhs) + ws_main_bytes(c, nrhs) + ws_plan_bytes(c->g, nrhs);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1057,6 +1153,38 @@ int ddqcd_set_schwarz(ddqcd_t c, int kind)
     if (kind != DDQCD_SCHWARZ_MULTIPLICATIVE && kind != DDQCD_SCHWARZ_ADDITIVE)
         return fail(c, DDQCD_ERR_ARG, "bad Schwarz variant");
     c->schwarz = kind;
+    return DDQCD_OK;
+}
+
+int ddqcd_workspace_size(ddqcd_t c, int nrhs, size_t *bytes)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (nrhs < 1 || !bytes) return fail(c, DDQCD_ERR_ARG, "bad workspace_size arguments");
+    *bytes = ws_total_bytes(c, nrhs);
+    return DDQCD_OK;
+}
+
+int ddqcd_set_workspace(ddqcd_t c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, DDQCD_ERR_ARG, "workspace must be 256-byte aligned");
+    if (c->ws || c->device >= 0 || !c->owned.empty())
+        return fail(c, DDQCD_ERR_STATE, "set_workspace must come before load_gauge, once per context");
+    int nrhs = 0;
+    while (nrhs < 4096 && ws_total_bytes(c, nrhs + 1) <= bytes) nrhs++;
+    if (nrhs == 0)
+        return fail(c, DDQCD_ERR_NOMEM, "the workspace is smaller than ddqcd_workspace_size(ctx, 1) = " +
+                                            std::to_string(ws_total_bytes(c, 1)));
+    c->ws = (unsigned char *)dev_ptr;
+    c->ws_bytes = bytes;
+    c->ws_plan_bytes = ws_plan_bytes(c->g, nrhs);
+    c->ws_plan = c->ws + (bytes - c->ws_plan_bytes) / 256 * 256;
+    c->ws_plan_bytes = bytes - (size_t)(c->ws_plan - c->ws);
+    c->ws_nrhs = nrhs;
+    // the reduction area of the solves this context leads, at the bottom
+    c->res_dev = (double2 *)c->ws;
+    c->ws_used = ws_result_bytes(nrhs);
+    c->res_cap = std::max(nrhs, 64);
     return DDQCD_OK;
 }
 

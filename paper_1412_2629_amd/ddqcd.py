@@ -18,7 +18,7 @@ PREC = {"f64": FP64, "f32": FP32, "f16": FP16, "bf16": BF16, FP64: FP64, FP32: F
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
 
-EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
+EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_workspace_size", "ddqcd_set_workspace", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
            "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_sap_noalloc", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
            "ddqcd_tune_sap",
@@ -53,6 +53,8 @@ def lib():
         vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.ddqcd_create.argtypes = [ctypes.POINTER(i), ctypes.POINTER(i), d, d, ctypes.POINTER(d), ctypes.POINTER(vp)]
         L.ddqcd_destroy.argtypes = [vp]
+        L.ddqcd_workspace_size.argtypes = [vp, i, ctypes.POINTER(ctypes.c_size_t)]
+        L.ddqcd_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.ddqcd_set_sap.argtypes = [vp, i, i, i, i]
         L.ddqcd_set_solver.argtypes = [vp, i, d, i]
         L.ddqcd_set_schedule.argtypes = [vp, i]
@@ -127,6 +129,24 @@ class Context:
     def _check(self, st, what):
         if st != OK:
             raise DDQCDError(st, f"{what}: {status_string(st)}: {lib().ddqcd_last_error(self._h).decode()}")
+
+    def workspace_size(self, nrhs=1):
+        """Bytes of device memory the context needs for nrhs right-hand sides
+        (ddqcd_workspace_size)."""
+        n = ctypes.c_size_t()
+        self._check(lib().ddqcd_workspace_size(self._h, nrhs, ctypes.byref(n)), "workspace_size")
+        return n.value
+
+    def set_workspace(self, ws):
+        """Hands the context a device tensor (uint8, contiguous) as its whole
+        device memory (ddqcd_set_workspace); the tensor is kept alive with the
+        context."""
+        import torch
+        if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+            raise TypeError("workspace must be a contiguous CUDA (HIP) tensor")
+        self._check(lib().ddqcd_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr()),
+                                              ws.numel() * ws.element_size()), "set_workspace")
+        self._workspace = ws
 
     def set_sap(self, n_cycles=16, n_mr=5, prec="f32", product="lane"):
         """product: "lane" (one right-hand side per workgroup), "tile" (four per

@@ -140,6 +140,32 @@ def test_tune_domain_host_paths():
     assert tuple(dom) == (2, 2, 2, 2) and ms.value == -1
 
 
+def test_workspace_host_paths():
+    """Workspace sizes grow with the number of right-hand sides by at least
+    the FGCR basis; misaligned, too small and repeated workspaces are refused
+    before any device work."""
+    L = ddqcd.lib()
+    st, h = _create((16, 16, 16, 16), (4, 4, 4, 4))
+    assert st == ddqcd.OK
+    try:
+        n = ctypes.c_size_t()
+        sizes = []
+        for k in (1, 2, 4):
+            assert L.ddqcd_workspace_size(h, k, ctypes.byref(n)) == ddqcd.OK
+            sizes.append(n.value)
+        V = 16 ** 4
+        assert sizes[0] > V * (576 + 576 + 576)                    # FP64 links, clover, C_e / C_o^-1
+        assert sizes[1] - sizes[0] >= V * 192 * (4 + 2 * 16)       # a slot: four FP64 vectors and the basis
+        assert sizes[2] - sizes[1] > sizes[1] - sizes[0]
+        assert L.ddqcd_workspace_size(h, 0, ctypes.byref(n)) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_workspace(h, ctypes.c_void_p(4096 + 8), sizes[2]) == ddqcd.ERR_ARG
+        assert L.ddqcd_set_workspace(h, ctypes.c_void_p(4096), sizes[0] - 1) == ddqcd.ERR_NOMEM
+        assert L.ddqcd_set_workspace(h, ctypes.c_void_p(1 << 20), sizes[1]) == ddqcd.OK
+        assert L.ddqcd_set_workspace(h, ctypes.c_void_p(1 << 20), sizes[1]) == ddqcd.ERR_STATE
+    finally:
+        assert L.ddqcd_destroy(h) == ddqcd.OK
+
+
 def test_status_strings():
     assert ddqcd.status_string(ddqcd.ERR_NOT_CONVERGED) == "DDQCD_ERR_NOT_CONVERGED"
     assert ddqcd.status_string(99) == "unknown status"
