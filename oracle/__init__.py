@@ -169,5 +169,44 @@ def fgcr(L, b, bc, U, C, Cinv, f, precond=True, n_cycles=16, n_mr=5, restart=16,
     return out
 
 
+def fgmres_dr(L, b, bc, U, C, Cinv, f, m, k, precond=True, n_cycles=16, n_mr=5, tol=1e-10, max_cycles=64,
+              x0=None, history=False, additive=False):
+    """Flexible GMRES with deflated restarts (basis m, k deflation vectors).
+    Returns (x, status, n_steps, relres[, history])."""
+    V = volume(L)
+    f = _c128(f, (V, 4, 3))
+    x = np.zeros((V, 4, 3), dtype=np.complex128) if x0 is None else _c128(x0, (V, 4, 3)).copy()
+    steps = ctypes.c_int(0)
+    rel = ctypes.c_double(0)
+    hist = np.zeros(max_cycles * m + 1)
+    b = b if b is not None else (1, 1, 1, 1)
+    Cinv = Cinv if Cinv is not None else C
+    st = lib().oracle_fgmres_dr(_i4(L), _i4(b), _d4(bc), _p(_c128(U, (V, 4, 3, 3))), _p(_c128(C, (V, 12, 12))),
+                                _p(_c128(Cinv, (V, 12, 12))), ctypes.c_int((2 if additive else 1) if precond else 0),
+                                ctypes.c_int(n_cycles), ctypes.c_int(n_mr), ctypes.c_int(m), ctypes.c_int(k),
+                                ctypes.c_double(tol), ctypes.c_int(max_cycles), _p(f), _p(x),
+                                ctypes.c_int(0 if x0 is None else 1), ctypes.byref(steps), ctypes.byref(rel), _p(hist))
+    out = (x, st, steps.value, rel.value)
+    if history:
+        n = int(np.count_nonzero(hist))
+        return out + (hist[:n],)
+    return out
+
+
+def harmonic_ritz(Hbar, k):
+    """The oracle's k harmonic Ritz pairs of smallest magnitude of the flexible
+    Arnoldi relation with Hessenberg-like Hbar ((m+1) x m): (theta, P), P an
+    orthonormal m x k basis of their vectors."""
+    Hbar = np.ascontiguousarray(Hbar, dtype=np.complex128)
+    m = Hbar.shape[1]
+    assert Hbar.shape == (m + 1, m)
+    P = np.zeros((m, k), dtype=np.complex128)
+    th = np.zeros(k, dtype=np.complex128)
+    st = lib().oracle_harmonic_ritz(ctypes.c_int(m), _p(Hbar), ctypes.c_int(k), _p(P), _p(th))
+    if st != OK:
+        raise ValueError(f"oracle status {st}")
+    return th, P
+
+
 def num_threads():
     return int(lib().oracle_num_threads())

@@ -764,6 +764,428 @@ done:
     return status;
 }
 
+/* ------------------------------------------------------------------ */
+/* flexible GMRES with deflated restarts (outer solver, Sec. II-C)     */
+/* ------------------------------------------------------------------ */
+
+/* Small dense complex matrices are row-major: M[i*ld + j]. */
+
+/* Least squares min_y |c - H y| for H (rows x cols, rows > cols, full column
+   rank), by Householder QR; returns |c - H y|. */
+static double small_lsq(int rows, int cols, const cplx *H, int ldh, const cplx *c, cplx *y)
+{
+    cplx *A = malloc(sizeof(cplx) * rows * cols), *b = malloc(sizeof(cplx) * rows);
+    for (int i = 0; i < rows; i++) {
+        for (int j = 0; j < cols; j++) A[i * cols + j] = H[i * ldh + j];
+        b[i] = c[i];
+    }
+    for (int j = 0; j < cols; j++) {
+        /* Householder vector u = x + e^{i arg x_0} |x| e_0 for column j, rows j.. */
+        double nx = 0;
+        for (int i = j; i < rows; i++) nx += creal(conj(A[i * cols + j]) * A[i * cols + j]);
+        nx = sqrt(nx);
+        if (nx == 0) continue;
+        cplx x0 = A[j * cols + j];
+        cplx ph = cabs(x0) > 0 ? x0 / cabs(x0) : 1.0;
+        cplx *u = malloc(sizeof(cplx) * rows);
+        for (int i = 0; i < rows; i++) u[i] = i >= j ? A[i * cols + j] : 0;
+        u[j] += ph * nx;
+        double uu = 0;
+        for (int i = j; i < rows; i++) uu += creal(conj(u[i]) * u[i]);
+        /* apply (1 - 2 u u^H / u^H u) to the remaining columns and to b */
+        for (int q = j; q < cols; q++) {
+            cplx t = 0;
+            for (int i = j; i < rows; i++) t += conj(u[i]) * A[i * cols + q];
+            t *= 2.0 / uu;
+            for (int i = j; i < rows; i++) A[i * cols + q] -= t * u[i];
+        }
+        cplx t = 0;
+        for (int i = j; i < rows; i++) t += conj(u[i]) * b[i];
+        t *= 2.0 / uu;
+        for (int i = j; i < rows; i++) b[i] -= t * u[i];
+        free(u);
+    }
+    for (int j = cols - 1; j >= 0; j--) {
+        cplx t = b[j];
+        for (int q = j + 1; q < cols; q++) t -= A[j * cols + q] * y[q];
+        y[j] = t / A[j * cols + j];
+    }
+    double res = 0;
+    for (int i = cols; i < rows; i++) res += creal(conj(b[i]) * b[i]);
+    free(A);
+    free(b);
+    return sqrt(res);
+}
+
+/* Solves M X = B (M n x n, B n x nr) by Gaussian elimination with partial
+   pivoting; returns nonzero if M is singular. */
+static int small_solve(int n, const cplx *M, int nr, cplx *B)
+{
+    cplx *A = malloc(sizeof(cplx) * n * n);
+    memcpy(A, M, sizeof(cplx) * n * n);
+    int bad = 0;
+    for (int c = 0; c < n && !bad; c++) {
+        int p = c;
+        for (int r = c + 1; r < n; r++)
+            if (cabs(A[r * n + c]) > cabs(A[p * n + c])) p = r;
+        if (cabs(A[p * n + c]) == 0) { bad = 1; break; }
+        if (p != c) {
+            for (int q = 0; q < n; q++) { cplx t = A[c * n + q]; A[c * n + q] = A[p * n + q]; A[p * n + q] = t; }
+            for (int q = 0; q < nr; q++) { cplx t = B[c * nr + q]; B[c * nr + q] = B[p * nr + q]; B[p * nr + q] = t; }
+        }
+        for (int r = c + 1; r < n; r++) {
+            cplx f = A[r * n + c] / A[c * n + c];
+            for (int q = c; q < n; q++) A[r * n + q] -= f * A[c * n + q];
+            for (int q = 0; q < nr; q++) B[r * nr + q] -= f * B[c * nr + q];
+        }
+    }
+    for (int c = n - 1; c >= 0 && !bad; c--)
+        for (int q = 0; q < nr; q++) {
+            cplx t = B[c * nr + q];
+            for (int j = c + 1; j < n; j++) t -= A[c * n + j] * B[j * nr + q];
+            B[c * nr + q] = t / A[c * n + c];
+        }
+    free(A);
+    return bad;
+}
+
+/* Eigenvalues and eigenvectors of a general complex n x n matrix B: reduction
+   to upper Hessenberg form by Householder reflections, then the shifted QR
+   iteration (Givens rotations, Wilkinson shift, deflation at negligible
+   subdiagonal entries) to the Schur form B = Z T Z^H, and eigenvectors of the
+   triangular T by back substitution, mapped back with Z.  lam[i] and the
+   columns of X (row-major n x n, X[r*n+i]) hold the pairs. */
+static void small_eig(int n, const cplx *B, cplx *lam, cplx *X)
+{
+    cplx *T = malloc(sizeof(cplx) * n * n), *Z = malloc(sizeof(cplx) * n * n);
+    memcpy(T, B, sizeof(cplx) * n * n);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) Z[i * n + j] = i == j;
+    /* Hessenberg reduction: T <- Q^H T Q, Z <- Z Q */
+    for (int j = 0; j + 2 < n; j++) {
+        double nx = 0;
+        for (int i = j + 1; i < n; i++) nx += creal(conj(T[i * n + j]) * T[i * n + j]);
+        nx = sqrt(nx);
+        if (nx == 0) continue;
+        cplx *u = calloc(n, sizeof(cplx));
+        cplx x0 = T[(j + 1) * n + j];
+        cplx ph = cabs(x0) > 0 ? x0 / cabs(x0) : 1.0;
+        for (int i = j + 1; i < n; i++) u[i] = T[i * n + j];
+        u[j + 1] += ph * nx;
+        double uu = 0;
+        for (int i = j + 1; i < n; i++) uu += creal(conj(u[i]) * u[i]);
+        for (int q = 0; q < n; q++) {   /* rows: T <- (1 - 2uu^H/uu) T */
+            cplx t = 0;
+            for (int i = j + 1; i < n; i++) t += conj(u[i]) * T[i * n + q];
+            t *= 2.0 / uu;
+            for (int i = j + 1; i < n; i++) T[i * n + q] -= t * u[i];
+        }
+        for (int r = 0; r < n; r++) {   /* columns: T <- T (1 - 2uu^H/uu), Z likewise */
+            cplx t = 0, tz = 0;
+            for (int i = j + 1; i < n; i++) {
+                t += T[r * n + i] * u[i];
+                tz += Z[r * n + i] * u[i];
+            }
+            t *= 2.0 / uu;
+            tz *= 2.0 / uu;
+            for (int i = j + 1; i < n; i++) {
+                T[r * n + i] -= t * conj(u[i]);
+                Z[r * n + i] -= tz * conj(u[i]);
+            }
+        }
+        free(u);
+        for (int i = j + 2; i < n; i++) T[i * n + j] = 0;
+    }
+    /* shifted QR iteration on the active block [lo, hi] */
+    int hi = n - 1, iter = 0;
+    while (hi > 0 && iter < 100 * n) {
+        /* deflate */
+        int l = hi;
+        while (l > 0) {
+            double s = cabs(T[(l - 1) * n + l - 1]) + cabs(T[l * n + l]);
+            if (cabs(T[l * n + l - 1]) <= 1e-15 * (s > 0 ? s : 1.0)) {
+                T[l * n + l - 1] = 0;
+                break;
+            }
+            l--;
+        }
+        if (l == hi) {
+            hi--;
+            iter = 0;
+            continue;
+        }
+        iter++;
+        /* Wilkinson shift from the trailing 2x2 block, or an exceptional shift */
+        cplx a = T[(hi - 1) * n + hi - 1], b2 = T[(hi - 1) * n + hi], c2 = T[hi * n + hi - 1], d = T[hi * n + hi];
+        cplx tr = a + d, det = a * d - b2 * c2, disc = csqrt(tr * tr / 4 - det);
+        cplx mu1 = tr / 2 + disc, mu2 = tr / 2 - disc;
+        cplx mu = cabs(mu1 - d) < cabs(mu2 - d) ? mu1 : mu2;
+        if (iter % 20 == 0) mu = d + cabs(T[hi * n + hi - 1]);
+        /* QR of (T - mu) on rows/cols l..hi by Givens rotations, then RQ + mu */
+        int nb = hi - l + 1;
+        cplx *cs = malloc(sizeof(cplx) * nb), *sn = malloc(sizeof(cplx) * nb);
+        for (int i = l; i <= hi; i++) T[i * n + i] -= mu;
+        for (int i = l; i < hi; i++) {
+            cplx x = T[i * n + i], y = T[(i + 1) * n + i];
+            double r = sqrt(creal(conj(x) * x) + creal(conj(y) * y));
+            cplx cc = r > 0 ? x / r : 1.0, ss = r > 0 ? y / r : 0.0;
+            cs[i - l] = cc;
+            sn[i - l] = ss;
+            for (int q = i; q < n; q++) {   /* G^H rows i, i+1 */
+                cplx t1 = T[i * n + q], t2 = T[(i + 1) * n + q];
+                T[i * n + q] = conj(cc) * t1 + conj(ss) * t2;
+                T[(i + 1) * n + q] = -ss * t1 + cc * t2;
+            }
+        }
+        for (int i = l; i < hi; i++) {   /* multiply by G on the right: columns i, i+1 */
+            cplx cc = cs[i - l], ss = sn[i - l];
+            for (int r = 0; r <= (i + 1 < hi ? i + 1 : hi); r++) {
+                cplx t1 = T[r * n + i], t2 = T[r * n + i + 1];
+                T[r * n + i] = cc * t1 + ss * t2;
+                T[r * n + i + 1] = -conj(ss) * t1 + conj(cc) * t2;
+            }
+            for (int r = 0; r < n; r++) {
+                cplx t1 = Z[r * n + i], t2 = Z[r * n + i + 1];
+                Z[r * n + i] = cc * t1 + ss * t2;
+                Z[r * n + i + 1] = -conj(ss) * t1 + conj(cc) * t2;
+            }
+        }
+        for (int i = l; i <= hi; i++) T[i * n + i] += mu;
+        free(cs);
+        free(sn);
+    }
+    for (int i = 0; i < n; i++) lam[i] = T[i * n + i];
+    /* eigenvectors of T, then X = Z Y */
+    double tn = 0;
+    for (int i = 0; i < n * n; i++) tn += cabs(T[i]);
+    cplx *Y = calloc(n, sizeof(cplx));
+    for (int e = 0; e < n; e++) {
+        for (int i = 0; i < n; i++) Y[i] = 0;
+        Y[e] = 1;
+        for (int j = e - 1; j >= 0; j--) {
+            cplx t = 0;
+            for (int q = j + 1; q <= e; q++) t -= T[j * n + q] * Y[q];
+            cplx den = T[j * n + j] - lam[e];
+            if (cabs(den) < 1e-14 * tn) den = 1e-14 * tn;
+            Y[j] = t / den;
+        }
+        double nrm = 0;
+        for (int r = 0; r < n; r++) {
+            cplx v = 0;
+            for (int q = 0; q <= e; q++) v += Z[r * n + q] * Y[q];
+            X[r * n + e] = v;
+            nrm += creal(conj(v) * v);
+        }
+        nrm = sqrt(nrm);
+        for (int r = 0; r < n; r++) X[r * n + e] /= nrm;
+    }
+    free(Y);
+    free(T);
+    free(Z);
+}
+
+/* The k harmonic Ritz pairs of smallest magnitude of a flexible Arnoldi
+   relation A Z_m = V_{m+1} Hbar (Hbar (m+1) x m, row-major): the pairs
+   (theta, g) with Hbar^H (Hbar g - theta [g; 0]) = 0, i.e. the eigenpairs of
+   H_m^{-H} Hbar^H Hbar with H_m the first m rows of Hbar.  P (m x k, row-major)
+   receives an orthonormal basis of span{g_1..g_k} (modified Gram-Schmidt, two
+   passes), theta the k values in increasing magnitude.  Returns nonzero if
+   H_m is singular. */
+int oracle_harmonic_ritz(int m, const cplx *Hbar, int k, cplx *P, cplx *theta)
+{
+    if (m < 1 || k < 1 || k > m) return OR_ERR_ARG;
+    cplx *G = malloc(sizeof(cplx) * m * m), *HmH = malloc(sizeof(cplx) * m * m);
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < m; j++) {
+            cplx s = 0;
+            for (int q = 0; q <= m; q++) s += conj(Hbar[q * m + i]) * Hbar[q * m + j];
+            G[i * m + j] = s;                     /* Hbar^H Hbar */
+            HmH[i * m + j] = conj(Hbar[j * m + i]);   /* H_m^H */
+        }
+    if (small_solve(m, HmH, m, G)) {
+        free(G);
+        free(HmH);
+        return OR_ERR_ARG;
+    }
+    cplx *lam = malloc(sizeof(cplx) * m), *X = malloc(sizeof(cplx) * m * m);
+    small_eig(m, G, lam, X);
+    int *ord = malloc(sizeof(int) * m);
+    for (int i = 0; i < m; i++) ord[i] = i;
+    for (int i = 0; i < m; i++)
+        for (int j = i + 1; j < m; j++)
+            if (cabs(lam[ord[j]]) < cabs(lam[ord[i]])) { int t = ord[i]; ord[i] = ord[j]; ord[j] = t; }
+    for (int q = 0; q < k; q++) {
+        theta[q] = lam[ord[q]];
+        for (int r = 0; r < m; r++) P[r * k + q] = X[r * m + ord[q]];
+        for (int pass = 0; pass < 2; pass++)
+            for (int p = 0; p < q; p++) {
+                cplx d = 0;
+                for (int r = 0; r < m; r++) d += conj(P[r * k + p]) * P[r * k + q];
+                for (int r = 0; r < m; r++) P[r * k + q] -= d * P[r * k + p];
+            }
+        double nrm = 0;
+        for (int r = 0; r < m; r++) nrm += creal(conj(P[r * k + q]) * P[r * k + q]);
+        nrm = sqrt(nrm);
+        for (int r = 0; r < m; r++) P[r * k + q] /= nrm;
+    }
+    free(ord);
+    free(lam);
+    free(X);
+    free(G);
+    free(HmH);
+    return OR_OK;
+}
+
+/* Solves A x = f by flexible GMRES with deflated restarts, right-preconditioned
+   by M (precond: 0 M = 1, 1 multiplicative SAP, 2 additive SAP).  A cycle runs
+   the flexible Arnoldi process z_j = M v_j, w = A z_j, modified Gram-Schmidt of
+   w against v_1..v_j (Hbar column j), v_{j+1} = w / |w|, up to m steps,
+   keeping A Z = V Hbar; after each step the least squares problem
+   min |c - Hbar y| gives the residual estimate, and the cycle ends at m steps
+   or when it falls below tol |f|.  Then x += Z y and the true residual f - A x
+   decides convergence.  Restart: with k > 0 deflation vectors after a full
+   cycle, the k harmonic Ritz vectors of smallest magnitude (oracle_harmonic_ritz)
+   and the least squares residual s = c - Hbar y form the orthonormal (m+1) x
+   (k+1) matrix P = [[P_k; 0], p] (p: s orthogonalised against them), and the
+   next cycle starts from V_{k+1} = V P, Z_k = Z P_k, Hbar_k = P^H Hbar P_k,
+   c = P^H s, with the Arnoldi process continued from step k+1 (orthogonalising
+   against all earlier v); otherwise (k = 0, or a cycle stopped early) it
+   restarts from the true residual.  n_steps counts preconditioner
+   applications; history (length max_cycles*m+1) gets the residual estimate of
+   every step, and the true residual at each cycle's end. */
+int oracle_fgmres_dr(const int L[4], const int b[4], const double bc[4], const cplx *U, const cplx *C,
+                     const cplx *Cinv, int precond, int n_cycles, int n_mr, int m, int k, double tol, int max_cycles,
+                     const cplx *f, cplx *x, int x_is_guess, int *n_steps, double *relres, double *history)
+{
+    if (m < 1 || k < 0 || k >= m || max_cycles < 1 || !(tol > 0)) return OR_ERR_ARG;
+    if (precond) {
+        int e = check_domains(L, b);
+        if (e) return e;
+    }
+    build_gamma();
+    long V = volume(L), n = V * 12;
+    cplx **Vb = malloc(sizeof(cplx *) * (m + 1)), **Zb = malloc(sizeof(cplx *) * m);
+    cplx *r = malloc(n * sizeof(cplx)), *w = malloc(n * sizeof(cplx));
+    cplx *H = calloc((size_t)(m + 1) * m, sizeof(cplx)), *c = calloc(m + 1, sizeof(cplx)), *y = calloc(m, sizeof(cplx));
+    for (int j = 0; j <= m; j++) Vb[j] = malloc(n * sizeof(cplx));
+    for (int j = 0; j < m; j++) Zb[j] = malloc(n * sizeof(cplx));
+    if (!x_is_guess) memset(x, 0, n * sizeof(cplx));
+    double fn = vnorm(n, f), rel = 0;
+    int steps = 0, status = OR_ERR_NOT_CONVERGED, hcount = 0, j0 = 0;
+    if (fn == 0) {
+        memset(x, 0, n * sizeof(cplx));
+        status = OR_OK;
+        goto done;
+    }
+    oracle_apply_A(L, bc, U, C, x, r);
+    for (long q = 0; q < n; q++) r[q] = f[q] - r[q];
+    rel = vnorm(n, r) / fn;
+    if (history) history[hcount++] = rel;
+    if (rel <= tol) { status = OR_OK; goto done; }
+    for (int cyc = 0; cyc < max_cycles; cyc++) {
+        if (j0 == 0) {   /* plain (re)start from the true residual */
+            double beta = vnorm(n, r);
+            for (long q = 0; q < n; q++) Vb[0][q] = r[q] / beta;
+            memset(H, 0, sizeof(cplx) * (m + 1) * m);
+            memset(c, 0, sizeof(cplx) * (m + 1));
+            c[0] = beta;
+        }
+        int jend = m;
+        for (int j = j0; j < m; j++) {
+            if (precond == 2) oracle_sap_additive(L, b, bc, U, C, Cinv, n_cycles, n_mr, Vb[j], Zb[j]);
+            else if (precond) oracle_sap(L, b, bc, U, C, Cinv, n_cycles, n_mr, Vb[j], Zb[j]);
+            else memcpy(Zb[j], Vb[j], n * sizeof(cplx));
+            oracle_apply_A(L, bc, U, C, Zb[j], w);
+            for (int i = 0; i <= j; i++) {
+                cplx h = vdot(n, Vb[i], w);
+                H[i * m + j] = h;
+                for (long q = 0; q < n; q++) w[q] -= h * Vb[i][q];
+            }
+            double hn = vnorm(n, w);
+            H[(j + 1) * m + j] = hn;
+            for (long q = 0; q < n; q++) Vb[j + 1][q] = w[q] / hn;
+            steps++;
+            double est = small_lsq(j + 2, j + 1, H, m, c, y) / fn;
+            if (history && hcount <= max_cycles * m) history[hcount++] = est;
+            if (est <= tol) { jend = j + 1; break; }
+        }
+        for (int j = 0; j < jend; j++)
+            for (long q = 0; q < n; q++) x[q] += y[j] * Zb[j][q];
+        oracle_apply_A(L, bc, U, C, x, r);
+        for (long q = 0; q < n; q++) r[q] = f[q] - r[q];
+        rel = vnorm(n, r) / fn;
+        if (history && hcount > 0) history[hcount - 1] = rel;
+        if (rel <= tol) { status = OR_OK; break; }
+        if (k == 0 || jend < m) { j0 = 0; continue; }
+        /* deflated restart */
+        cplx *s = malloc(sizeof(cplx) * (m + 1)), *Pk = malloc(sizeof(cplx) * m * k), *th = malloc(sizeof(cplx) * k);
+        cplx *P = calloc((size_t)(m + 1) * (k + 1), sizeof(cplx));
+        for (int i = 0; i <= m; i++) {
+            cplx t = c[i];
+            for (int j = 0; j < m; j++) t -= H[i * m + j] * y[j];
+            s[i] = t;
+        }
+        if (oracle_harmonic_ritz(m, H, k, Pk, th)) {
+            free(s); free(Pk); free(th); free(P);
+            j0 = 0;
+            continue;
+        }
+        for (int i = 0; i < m; i++)
+            for (int q = 0; q < k; q++) P[i * (k + 1) + q] = Pk[i * k + q];
+        for (int i = 0; i <= m; i++) P[i * (k + 1) + k] = s[i];
+        for (int pass = 0; pass < 2; pass++)
+            for (int q = 0; q < k; q++) {
+                cplx d = 0;
+                for (int i = 0; i <= m; i++) d += conj(P[i * (k + 1) + q]) * P[i * (k + 1) + k];
+                for (int i = 0; i <= m; i++) P[i * (k + 1) + k] -= d * P[i * (k + 1) + q];
+            }
+        double pn = 0;
+        for (int i = 0; i <= m; i++) pn += creal(conj(P[i * (k + 1) + k]) * P[i * (k + 1) + k]);
+        pn = sqrt(pn);
+        for (int i = 0; i <= m; i++) P[i * (k + 1) + k] /= pn;
+        /* new bases: V_{k+1} = V P, Z_k = Z P_k (through w and r as scratch) */
+        cplx **nV = malloc(sizeof(cplx *) * (k + 1)), **nZ = malloc(sizeof(cplx *) * k);
+        for (int q = 0; q <= k; q++) nV[q] = calloc(n, sizeof(cplx));
+        for (int q = 0; q < k; q++) nZ[q] = calloc(n, sizeof(cplx));
+        for (int q = 0; q <= k; q++)
+            for (int i = 0; i <= m; i++)
+                for (long t = 0; t < n; t++) nV[q][t] += Vb[i][t] * P[i * (k + 1) + q];
+        for (int q = 0; q < k; q++)
+            for (int i = 0; i < m; i++)
+                for (long t = 0; t < n; t++) nZ[q][t] += Zb[i][t] * P[i * (k + 1) + q];
+        for (int q = 0; q <= k; q++) { memcpy(Vb[q], nV[q], n * sizeof(cplx)); free(nV[q]); }
+        for (int q = 0; q < k; q++) { memcpy(Zb[q], nZ[q], n * sizeof(cplx)); free(nZ[q]); }
+        free(nV);
+        free(nZ);
+        /* Hbar_k = P^H Hbar P_k, c = P^H s */
+        cplx *Hn = calloc((size_t)(m + 1) * m, sizeof(cplx));
+        for (int a = 0; a <= k; a++)
+            for (int q = 0; q < k; q++) {
+                cplx t = 0;
+                for (int i = 0; i <= m; i++)
+                    for (int j = 0; j < m; j++) t += conj(P[i * (k + 1) + a]) * H[i * m + j] * P[j * (k + 1) + q];
+                Hn[a * m + q] = t;
+            }
+        memcpy(H, Hn, sizeof(cplx) * (m + 1) * m);
+        free(Hn);
+        memset(c, 0, sizeof(cplx) * (m + 1));
+        for (int a = 0; a <= k; a++) {
+            cplx t = 0;
+            for (int i = 0; i <= m; i++) t += conj(P[i * (k + 1) + a]) * s[i];
+            c[a] = t;
+        }
+        free(s); free(Pk); free(th); free(P);
+        j0 = k;
+    }
+done:
+    if (n_steps) *n_steps = steps;
+    if (relres) *relres = rel;
+    for (int j = 0; j <= m; j++) free(Vb[j]);
+    for (int j = 0; j < m; j++) free(Zb[j]);
+    free(Vb); free(Zb); free(r); free(w); free(H); free(c); free(y);
+    return status;
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

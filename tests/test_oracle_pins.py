@@ -475,3 +475,150 @@ def test_fgcr_zero_source_and_guess(oracle, dense_4444):
     x, st, steps, relres = oracle.fgcr(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], f, n_cycles=2, n_mr=2,
                                        max_cycles=1, restart=1, tol=1e-10)
     assert st == 6 and steps == 1 and relres < 1
+
+
+# ---------------------------------------------------------------------------
+# flexible GMRES with deflated restarts (Sec. II-C)
+# ---------------------------------------------------------------------------
+
+def _hessenberg_like(rng, m, dense_block=0):
+    """(m+1) x m: upper Hessenberg, or, after a deflated restart, with a dense
+    (k+1) x k leading block."""
+    H = np.triu(rng.standard_normal((m + 1, m)) + 1j * rng.standard_normal((m + 1, m)), -1)
+    if dense_block:
+        H[:dense_block + 1, :dense_block] = (rng.standard_normal((dense_block + 1, dense_block))
+                                             + 1j * rng.standard_normal((dense_block + 1, dense_block)))
+    return H
+
+
+@pytest.mark.parametrize("m,k,dense", [(6, 1, 0), (8, 3, 0), (8, 4, 3), (16, 6, 0), (16, 6, 5)])
+def test_harmonic_ritz_pairs(oracle, m, k, dense):
+    """The oracle's harmonic Ritz pairs are those of the generalized problem
+    (Hbar^H Hbar) g = theta H_m^H g (LAPACK through scipy): the k values of
+    smallest magnitude, and the span of their vectors."""
+    import scipy.linalg as sl
+    H = _hessenberg_like(np.random.default_rng(m * 10 + k + dense), m, dense)
+    th, P = oracle.harmonic_ritz(H, k)
+    w, vr = sl.eig(H.conj().T @ H, H[:m].conj().T)
+    o = np.argsort(np.abs(w))
+    assert np.allclose(th, w[o[:k]], rtol=1e-10, atol=1e-12)
+    assert np.allclose(P.conj().T @ P, np.eye(k), atol=1e-12)
+    Q, _ = np.linalg.qr(vr[:, o[:k]])
+    assert sl.subspace_angles(P, Q).max() < 1e-9
+    # the defining property of each pair: Hbar^H (Hbar g - theta [g; 0]) = 0
+    for q in range(k):
+        g = vr[:, o[q]]
+        assert np.linalg.norm(H.conj().T @ (H @ g - w[o[q]] * np.append(g, 0))) < 1e-9 * np.linalg.norm(H) ** 2
+
+
+def _arnoldi(A, r, m):
+    """m steps of Arnoldi (modified Gram-Schmidt): V (n x m+1), Hbar."""
+    n = len(r)
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    V[:, 0] = r / np.linalg.norm(r)
+    for j in range(m):
+        w = A @ V[:, j]
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[:, i], w)
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    return V, H
+
+
+@pytest.mark.parametrize("m,k", [(6, 2), (8, 3)])
+def test_fgmres_dr_deflated_restart_space(oracle, m, k):
+    """With M = 1: the first cycle is GMRES(m) (least squares over the Krylov
+    space of f); the second cycle minimises |f - A x| over x_1 plus the span of
+    the k harmonic Ritz vectors of the first cycle and the Krylov vectors
+    r_1, A r_1, ..., A^{m-k-1} r_1 (GMRES-DR's search space), built here from
+    dense numpy Arnoldi and scipy's generalized eigensolver."""
+    import scipy.linalg as sl
+    L = (2, 2, 2, 4)
+    U = inputs.random_gauge(L, 0.5, 83)
+    C = oracle.clover_field(L, U, 0.13, 1.5)
+    V = 32
+    f = inputs.gaussian_source(L, 84)
+    A = R.dense_operator(lambda v: oracle.apply_A(L, BC, U, C, v.reshape(V, 4, 3)), V * 12)
+    fv = f.reshape(-1)
+    # cycle 1: GMRES(m) from x0 = 0
+    Vb, H = _arnoldi(A, fv, m)
+    c = np.zeros(m + 1, dtype=np.complex128)
+    c[0] = np.linalg.norm(fv)
+    y, *_ = np.linalg.lstsq(H, c, rcond=None)
+    x1 = Vb[:, :m] @ y
+    x, st, steps, _ = oracle.fgmres_dr(L, None, BC, U, C, None, f, m, k, precond=False, tol=1e-300, max_cycles=1)
+    assert steps == m and rel(x.reshape(-1), x1) < 1e-11
+    # cycle 2 over the deflated space
+    w, vr = sl.eig(H.conj().T @ H, H[:m].conj().T)
+    o = np.argsort(np.abs(w))
+    Y = Vb[:, :m] @ vr[:, o[:k]]
+    r1 = fv - A @ x1
+    S = [Y[:, q] for q in range(k)] + [r1]
+    for _ in range(m - k - 1):
+        S.append(A @ S[-1])
+    S, _ = np.linalg.qr(np.stack(S, axis=1))
+    coef, *_ = np.linalg.lstsq(A @ S, r1, rcond=None)
+    x2 = x1 + S @ coef
+    x, st, steps, _ = oracle.fgmres_dr(L, None, BC, U, C, None, f, m, k, precond=False, tol=1e-300, max_cycles=2)
+    assert steps == 2 * m - k
+    assert rel(x.reshape(-1), x2) < 1e-9
+    # without deflation the second cycle is plain restarted GMRES(m) instead
+    x0d, _, _, _ = oracle.fgmres_dr(L, None, BC, U, C, None, f, m, 0, precond=False, tol=1e-300, max_cycles=2)
+    assert rel(x0d.reshape(-1), x2) > 1e-6
+
+
+def test_fgmres_dr_residual_estimates_are_gmres(oracle):
+    """Within the first cycle, the residual estimate after step j is GMRES(j)'s
+    minimum over the Krylov space (M = 1)."""
+    L = (2, 2, 2, 4)
+    U = inputs.random_gauge(L, 0.5, 85)
+    C = oracle.clover_field(L, U, 0.13, 1.5)
+    V = 32
+    f = inputs.gaussian_source(L, 86)
+    _, st, steps, _, hist = oracle.fgmres_dr(L, None, BC, U, C, None, f, 12, 4, precond=False, tol=1e-300,
+                                             max_cycles=1, history=True)
+    A = R.dense_operator(lambda v: oracle.apply_A(L, BC, U, C, v.reshape(V, 4, 3)), V * 12)
+    fv = f.reshape(-1)
+    K = [fv]
+    for _ in range(1, 12):
+        K.append(A @ K[-1])
+    fn = np.linalg.norm(fv)
+    for j in range(1, 12):
+        Q, _ = np.linalg.qr(np.stack(K[:j], axis=1))
+        y, *_ = np.linalg.lstsq(A @ Q, fv, rcond=None)
+        want = np.linalg.norm(fv - A @ Q @ y) / fn
+        assert abs(hist[j] - want) <= 1e-10 * max(want, 1e-3), j
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("m,k", [(8, 4), (16, 6)])
+def test_fgmres_dr_sap_dense_solve(oracle, dense_4444, m, k):
+    """FGMRES-DR with the SAP preconditioner (the paper's basis and deflation
+    sizes, Sec. IV-C) reaches LAPACK's dense solution."""
+    g = dense_4444
+    f = inputs.gaussian_source(g["L"], 107)
+    x, st, steps, relres = oracle.fgmres_dr(g["L"], g["b"], BC, g["U"], g["C"], g["Ci"], f, m, k, n_cycles=8,
+                                            n_mr=4, tol=1e-12)
+    assert st == 0 and relres <= 1e-12
+    assert rel(x.reshape(-1), np.linalg.solve(g["A"], f.reshape(-1))) < 1e-10
+
+
+def test_fgmres_dr_unpreconditioned_restarts_dense_solve(oracle):
+    """Many deflated restarts (M = 1, basis 6, 3 deflation vectors) still reach
+    the dense solution; the zero source and an exact guess take no step."""
+    L = (2, 2, 2, 2)
+    U = inputs.random_gauge(L, 0.5, 93)
+    C = oracle.clover_field(L, U, 0.12, 1.0)
+    f = inputs.gaussian_source(L, 94)
+    A = R.dense_operator(lambda v: oracle.apply_A(L, BC, U, C, v.reshape(16, 4, 3)), 192)
+    want = np.linalg.solve(A, f.reshape(-1))
+    x, st, steps, relres = oracle.fgmres_dr(L, None, BC, U, C, None, f, 6, 3, precond=False, tol=1e-12,
+                                            max_cycles=200)
+    assert st == 0 and rel(x.reshape(-1), want) < 1e-10
+    x0, st0, steps0, _ = oracle.fgmres_dr(L, None, BC, U, C, None, np.zeros_like(f), 6, 3, precond=False)
+    assert st0 == 0 and steps0 == 0 and not np.any(x0)
+    xg, stg, stepsg, _ = oracle.fgmres_dr(L, None, BC, U, C, None, f, 6, 3, precond=False,
+                                          x0=want.reshape(16, 4, 3))
+    assert stg == 0 and stepsg == 0
