@@ -66,7 +66,7 @@ class System:
         self.b = torch.from_numpy(np.ascontiguousarray(srcs[0] if len(srcs) == 1 else np.stack(srcs))).to(dev)
 
 
-def build(name, schedule, tune=False, schwarz="multiplicative", domain=None, product="lane"):
+def build(name, schedule, tune=False, schwarz="multiplicative", domain=None, product="lane", lattice=None):
     import dataclasses
 
     import numpy as np
@@ -76,6 +76,8 @@ def build(name, schedule, tune=False, schwarz="multiplicative", domain=None, pro
     if name == "C5":
         out = []
         for j, w in enumerate(configs.uneven_batch()):
+            if lattice is not None and j != lattice:
+                continue
             log(f"[bench] lattice {j} {w.lattice}: generating inputs")
             U = inputs.random_gauge(w.lattice, w.eps, w.gauge_seed)
             src = inputs.gaussian_source(w.lattice, w.source_seed)
@@ -149,6 +151,10 @@ def main():
                     help="block-solve product form: one right-hand side per workgroup, or tiles of four with the "
                          "link products on VALU, FP32 MFMA or BF16-input MFMA (4^4 domains, FP16 storage); auto: "
                          "tuned with the domain shape by ddqcd_tune_sap")
+    ap.add_argument("--outer", default="fgcr",
+                    help="outer solver: fgcr, or fgmres_dr:M:K (flexible GMRES with deflated restarts, basis M, "
+                         "K deflation vectors)")
+    ap.add_argument("--lattice", type=int, default=None, help="uneven batch: solve only this lattice")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the listed domain shapes (and one right-hand side per workgroup) instead of autotuning "
                          "them per lattice")
@@ -168,7 +174,12 @@ def main():
     t_tune = time.perf_counter()
     systems = build(args.workload, args.schedule, tune=not args.no_tune, schwarz=args.schwarz,
                     domain=tuple(int(v) for v in args.domain.split(",")) if args.domain else None,
-                    product=args.product)
+                    product=args.product, lattice=args.lattice)
+    if args.outer != "fgcr":
+        kind, m, k = args.outer.split(":")
+        for s in systems:
+            s.ctx.set_solver(int(m), s.w.tol, 64)
+            s.ctx.set_outer(kind, int(k))
     t_tune = time.perf_counter() - t_tune
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
@@ -249,13 +260,15 @@ def main():
               f"{[(l, d, sum(1 for s in systems if (s.w.lattice, s.w.domain) == (l, d))) for l, d in doms]}, "
               f"kappa in [0.12, 0.136], c_sw 1.5, eps in [0.3, 0.6], FP16-storage SAP {w0.n_cycles}x{w0.n_mr}, "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, one ddqcd_solve_batch call, schedule {args.schedule}, "
-              f"{args.schwarz} Schwarz")
+              f"{args.schwarz} Schwarz, outer {args.outer}"
+              + (f", lattice {args.lattice} only" if args.lattice is not None else ""))
         batch = len(systems)
     else:
         wl = (f"{w0.name}: lattice {w0.lattice}, kappa {w0.kappa}, c_sw {w0.csw}, eps {w0.eps}, "
               f"domains {w0.domain}, SAP {w0.n_cycles} cycles x {w0.n_mr} MR ({w0.prec}), "
               f"FGCR restart {w0.restart} (f64), tol {w0.tol}, {len(systems[0].srcs)} right-hand side(s), "
-              f"schedule {args.schedule}, {args.schwarz} Schwarz, block-solve products {systems[0].product}"
+              f"schedule {args.schedule}, {args.schwarz} Schwarz, outer {args.outer}, "
+              f"block-solve products {systems[0].product}"
               + (" (domain shape and products autotuned)" if not args.no_tune and not args.domain
                  and args.product == "auto" else ""))
         batch = len(systems[0].srcs)

@@ -177,6 +177,21 @@ int ddqcd_set_schwarz(ddqcd_t ctx, int kind);
 int ddqcd_workspace_size(ddqcd_t ctx, int nrhs, size_t *bytes);
 int ddqcd_set_workspace(ddqcd_t ctx, void *dev_ptr, size_t bytes);
 
+/* The outer solver of ddqcd_solve and ddqcd_solve_batch (Sec. II-C).
+ * DDQCD_OUTER_FGCR (the default): flexible GCR, restart = basis vectors per
+ * cycle, all right-hand sides in lockstep.  DDQCD_OUTER_FGMRES_DR: flexible
+ * GMRES with deflated restarts, the paper's outer solver (Table I): restart =
+ * maximum basis size m, deflate = k harmonic Ritz vectors of smallest magnitude
+ * kept at each restart (0 <= k < m; the paper uses m = 8, k = 4 and m = 16,
+ * k = 6, Sec. IV-C), right-hand sides one after the other.  Both keep the
+ * orthogonalisation, residuals and solution update in FP64 and stop on the
+ * true residual recomputed at each cycle's end.  ddqcd_solve_batch needs equal
+ * settings on all contexts.  DDQCD_ERR_ARG for values out of range,
+ * DDQCD_ERR_STATE on a workspace context that already has work slots (their
+ * basis size is fixed). */
+typedef enum { DDQCD_OUTER_FGCR = 0, DDQCD_OUTER_FGMRES_DR = 1 } ddqcd_outer;
+int ddqcd_set_outer(ddqcd_t ctx, int kind, int deflate);
+
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the
  * true relative residual |b - A x|/|b| (Sec. IV-C1), max_cycles >= 1. */
 int ddqcd_set_solver(ddqcd_t ctx, int restart, double tol, int max_cycles);

@@ -70,6 +70,7 @@ struct Slot {
     double2 *x = nullptr, *r = nullptr, *b = nullptr;                            // FP64 vectors
     double2 *Z = nullptr, *W = nullptr;                                          // FGCR basis
     int zw_restart = 0;
+    double2 *rcoef = nullptr;   // restart recombination matrix (FGMRES-DR)
     Blas blas;
 };
 
@@ -103,6 +104,7 @@ struct Plan {
 };
 
 constexpr int N_XCD = 8;
+constexpr int RCOEF = 24 * 24;   // entries of a slot's restart recombination matrix
 constexpr size_t MAX_PLANS = 32;
 
 }  // namespace
@@ -112,6 +114,7 @@ struct ddqcd_ctx {
     double kappa = 0, csw = 0;
     int n_cycles = 16, n_mr = 5, sap_prec = DDQCD_FP32, product = DDQCD_PRODUCT_LANE;
     int restart = 16, max_cycles = 64;
+    int outer = DDQCD_OUTER_FGCR, deflate = 0;   // outer solver, FGMRES-DR deflation vectors
     double tol = 1e-10;
     int schedule = DDQCD_SCHED_SWEEPS;
     int schwarz = DDQCD_SCHWARZ_MULTIPLICATIVE;
@@ -257,15 +260,24 @@ int ensure_slots(ddqcd_t c, int n)
         if ((e = alloc(c, &sl->blas.partial, sizeof(double2) * BLAS_NBLK * 32))) return e;
         if ((e = alloc(c, &sl->blas.result, sizeof(double2) * 32))) return e;
         if ((e = alloc(c, &sl->blas.coef, sizeof(double2) * 32))) return e;
+        if ((e = alloc(c, &sl->rcoef, sizeof(double2) * RCOEF))) return e;
         c->slots.push_back(std::move(sl));
     }
     return DDQCD_OK;
 }
 
-// FGCR's z and w columns (at least 5: the BiCGstab work vectors)
+// columns of each of the two basis arrays: FGCR's z and w (restart), FGMRES-DR's
+// z and v with room for the restart recombination (restart + deflate + 2), at
+// least 5 (the BiCGstab work vectors)
+int basis_columns(ddqcd_t c)
+{
+    const int outer = c->outer == DDQCD_OUTER_FGMRES_DR ? c->restart + c->deflate + 2 : c->restart;
+    return std::max(outer, 5);
+}
+
 int ensure_basis(ddqcd_t c, Slot &sl, int columns = 0)
 {
-    const int want = std::max(std::max(columns, c->restart), 5);
+    const int want = std::max(columns, basis_columns(c));
     if (sl.zw_restart >= want) return DDQCD_OK;
     const size_t nc = (size_t)ncomplex(c->g);
     int e;
@@ -884,6 +896,384 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
     return status;
 }
 
+// ---- flexible GMRES with deflated restarts ------------------------------------
+//
+// Small dense complex matrices on the host are row-major vectors.
+
+// min |c - H y| (H rows x cols, row stride ld, full column rank): QR of H by
+// modified Gram-Schmidt with a second orthogonalisation pass, R y = Q^H c;
+// returns |c - H y|, evaluated directly.
+double lsq_mgs(int rows, int cols, const C *H, int ld, const C *c, C *y)
+{
+    std::vector<C> Q((size_t)rows * cols), Rm((size_t)cols * cols, 0.0);
+    for (int j = 0; j < cols; j++) {
+        for (int i = 0; i < rows; i++) Q[(size_t)i * cols + j] = H[(size_t)i * ld + j];
+        for (int pass = 0; pass < 2; pass++)
+            for (int p = 0; p < j; p++) {
+                C d = 0;
+                for (int i = 0; i < rows; i++) d += std::conj(Q[(size_t)i * cols + p]) * Q[(size_t)i * cols + j];
+                Rm[(size_t)p * cols + j] += d;
+                for (int i = 0; i < rows; i++) Q[(size_t)i * cols + j] -= d * Q[(size_t)i * cols + p];
+            }
+        double nq = 0;
+        for (int i = 0; i < rows; i++) nq += std::norm(Q[(size_t)i * cols + j]);
+        nq = std::sqrt(nq);
+        Rm[(size_t)j * cols + j] = nq;
+        for (int i = 0; i < rows; i++) Q[(size_t)i * cols + j] /= nq;
+    }
+    for (int j = cols - 1; j >= 0; j--) {
+        C t = 0;
+        for (int i = 0; i < rows; i++) t += std::conj(Q[(size_t)i * cols + j]) * c[i];
+        for (int p = j + 1; p < cols; p++) t -= Rm[(size_t)j * cols + p] * y[p];
+        y[j] = t / Rm[(size_t)j * cols + j];
+    }
+    double res = 0;
+    for (int i = 0; i < rows; i++) {
+        C t = c[i];
+        for (int j = 0; j < cols; j++) t -= H[(size_t)i * ld + j] * y[j];
+        res += std::norm(t);
+    }
+    return std::sqrt(res);
+}
+
+// x = M^-1 b for a small n x n matrix (Gaussian elimination, partial pivoting);
+// false if singular
+bool small_solve(int n, std::vector<C> M, std::vector<C> &x)
+{
+    for (int col = 0; col < n; col++) {
+        int p = col;
+        for (int r = col + 1; r < n; r++)
+            if (std::abs(M[(size_t)r * n + col]) > std::abs(M[(size_t)p * n + col])) p = r;
+        if (!(std::abs(M[(size_t)p * n + col]) > 0)) return false;
+        if (p != col) {
+            for (int q = 0; q < n; q++) std::swap(M[(size_t)p * n + q], M[(size_t)col * n + q]);
+            std::swap(x[p], x[col]);
+        }
+        for (int r = col + 1; r < n; r++) {
+            const C f = M[(size_t)r * n + col] / M[(size_t)col * n + col];
+            for (int q = col; q < n; q++) M[(size_t)r * n + q] -= f * M[(size_t)col * n + q];
+            x[r] -= f * x[col];
+        }
+    }
+    for (int r = n - 1; r >= 0; r--) {
+        C t = x[r];
+        for (int q = r + 1; q < n; q++) t -= M[(size_t)r * n + q] * x[q];
+        x[r] = t / M[(size_t)r * n + r];
+    }
+    return true;
+}
+
+// Eigenvalues of a small general complex matrix: QR iterations on the full
+// matrix (Wilkinson shift from the trailing 2x2 block, the QR factor by
+// modified Gram-Schmidt), deflating the last row of the active block when
+// its off-diagonal part is negligible.
+std::vector<C> small_eigenvalues(int n, std::vector<C> A)
+{
+    std::vector<C> lam;
+    double an = 0;
+    for (const C &v : A) an += std::norm(v);
+    an = std::sqrt(an);
+    int act = n, iters = 0;
+    while (act > 0) {
+        const int a = act - 1;
+        double off = 0;
+        for (int j = 0; j < a; j++) off += std::norm(A[(size_t)a * n + j]);
+        if (act == 1 || std::sqrt(off) <= 1e-15 * an || iters > 200) {
+            lam.push_back(A[(size_t)a * n + a]);
+            act--;
+            iters = 0;
+            continue;
+        }
+        iters++;
+        const C p = A[(size_t)(a - 1) * n + a - 1], q = A[(size_t)(a - 1) * n + a], r = A[(size_t)a * n + a - 1],
+                d = A[(size_t)a * n + a];
+        const C half = 0.5 * (p + d), disc = std::sqrt(0.25 * (p - d) * (p - d) + q * r);
+        C mu = std::abs(half + disc - d) < std::abs(half - disc - d) ? half + disc : half - disc;
+        if (iters % 25 == 0) mu = d + std::sqrt(off);   // exceptional shift
+        std::vector<C> Qm((size_t)act * act), Rm((size_t)act * act, 0.0);
+        for (int j = 0; j < act; j++) {
+            for (int i = 0; i < act; i++) Qm[(size_t)i * act + j] = A[(size_t)i * n + j] - (i == j ? mu : C(0));
+            for (int pass = 0; pass < 2; pass++)
+                for (int pp = 0; pp < j; pp++) {
+                    C dd = 0;
+                    for (int i = 0; i < act; i++) dd += std::conj(Qm[(size_t)i * act + pp]) * Qm[(size_t)i * act + j];
+                    Rm[(size_t)pp * act + j] += dd;
+                    for (int i = 0; i < act; i++) Qm[(size_t)i * act + j] -= dd * Qm[(size_t)i * act + pp];
+                }
+            double nq = 0;
+            for (int i = 0; i < act; i++) nq += std::norm(Qm[(size_t)i * act + j]);
+            nq = std::sqrt(nq);
+            Rm[(size_t)j * act + j] = nq;
+            for (int i = 0; i < act; i++) Qm[(size_t)i * act + j] = nq > 0 ? Qm[(size_t)i * act + j] / nq : C(0);
+        }
+        for (int i = 0; i < act; i++)   // A_act = R Q + mu
+            for (int j = 0; j < act; j++) {
+                C t = i == j ? mu : C(0);
+                for (int l = i; l < act; l++) t += Rm[(size_t)i * act + l] * Qm[(size_t)l * act + j];
+                A[(size_t)i * n + j] = t;
+            }
+    }
+    return lam;
+}
+
+// Orthonormal basis (m x k, row-major) of the span of the k harmonic Ritz
+// vectors of smallest |theta| of the relation A Z = V Hbar (Hbar (m+1) x m,
+// last row h e_m^T): the eigenvectors of H_m + |h|^2 H_m^-H e_m e_m^H, found by
+// inverse iteration at each selected eigenvalue, each start vector and
+// iterate orthogonalised against the vectors already taken (so a cluster of
+// close eigenvalues yields its invariant subspace).
+bool harmonic_ritz_basis(int m, int k, const std::vector<C> &H, std::vector<C> &P)
+{
+    std::vector<C> Hm((size_t)m * m), HmH((size_t)m * m);
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < m; j++) {
+            Hm[(size_t)i * m + j] = H[(size_t)i * m + j];
+            HmH[(size_t)i * m + j] = std::conj(H[(size_t)j * m + i]);
+        }
+    std::vector<C> f(m, 0.0);
+    f[m - 1] = 1.0;
+    if (!small_solve(m, HmH, f)) return false;
+    const double h2 = std::norm(H[(size_t)m * m + m - 1]);
+    std::vector<C> B = Hm;
+    for (int i = 0; i < m; i++) B[(size_t)i * m + m - 1] += h2 * f[i];
+    std::vector<C> lam = small_eigenvalues(m, B);
+    std::sort(lam.begin(), lam.end(), [](const C &a, const C &b) { return std::abs(a) < std::abs(b); });
+    double bn = 0;
+    for (const C &v : B) bn += std::norm(v);
+    bn = std::sqrt(bn);
+    P.assign((size_t)m * k, 0.0);
+    for (int q = 0; q < k; q++) {
+        const C shift = lam[q] + C(1e-13 * bn, 1e-13 * bn);
+        std::vector<C> Ms = B;
+        for (int i = 0; i < m; i++) Ms[(size_t)i * m + i] -= shift;
+        std::vector<C> v(m);
+        for (int i = 0; i < m; i++) v[i] = C(1.0 + 0.1 * i, 0.3 * (i % 3));
+        for (int it = 0; it < 4; it++) {
+            for (int pass = 0; pass < 2; pass++)
+                for (int p = 0; p < q; p++) {
+                    C d = 0;
+                    for (int i = 0; i < m; i++) d += std::conj(P[(size_t)i * k + p]) * v[i];
+                    for (int i = 0; i < m; i++) v[i] -= d * P[(size_t)i * k + p];
+                }
+            double nv = 0;
+            for (const C &t : v) nv += std::norm(t);
+            nv = std::sqrt(nv);
+            for (C &t : v) t /= nv;
+            if (it < 3 && !small_solve(m, Ms, v)) return false;
+        }
+        for (int i = 0; i < m; i++) P[(size_t)i * k + q] = v[i];
+    }
+    return true;
+}
+
+// Solves A x = b for one system (x, b: the slot's FP64 vectors; x holds a
+// guess if guess) by FGMRES-DR(m = restart, k = deflate), right-preconditioned
+// by the context's SAP: the same algorithm as the oracle's (flexible Arnoldi,
+// least squares residual estimate after each step, x += Z y and the true FP64
+// residual at each cycle's end, deflated restart from the harmonic Ritz
+// vectors and the least squares residual), with classical Gram-Schmidt
+// repeated once when the new vector loses more than half its norm.
+int fgmres_dr(const Sys &y, bool guess, ddqcd_info &info, hipStream_t s)
+{
+    ddqcd_t c = y.c;
+    Slot &sl = *y.sl;
+    const int m = c->restart, k = c->deflate;
+    const long n = ncomplex(c->g);
+    int e;
+    if ((e = ensure_basis(c, sl))) return e;
+    double2 *Vb = sl.W, *Zb = sl.Z;
+    auto Vc = [&](int j) { return Vb + (long)j * n; };
+    auto Zc = [&](int j) { return Zb + (long)j * n; };
+    double tsap = 0, tA = 0, tgs = 0, tother = 0;
+    Clock clk(s);
+    double2 h[32];
+    auto fetch = [&](int cnt) -> int {
+        HIPCHK(c, hipMemcpyAsync(h, sl.blas.result, sizeof(double2) * cnt, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return DDQCD_OK;
+    };
+    auto put = [&](const std::vector<C> &v, double2 *dst) -> int {
+        HIPCHK(c, hipMemcpyAsync(dst, v.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice, s));
+        return DDQCD_OK;
+    };
+    info = ddqcd_info{};
+    if (!guess) HIPCHK(c, zero(sl.x, n, s));
+    HIPCHK(c, norm2(sl.blas, sl.b, n, s));
+    if ((e = fetch(1))) return e;
+    const double bn = std::sqrt(h[0].x);
+    if (!std::isfinite(bn)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite right-hand side");
+    if (bn == 0) {
+        HIPCHK(c, zero(sl.x, n, s));
+        info.converged = 1;
+        return DDQCD_OK;
+    }
+    double rn;
+    {
+        Timer t(clk, &tA);
+        if ((e = apply_A64(c, sl.x, sl.r, s))) return e;
+    }
+    HIPCHK(c, residual(sl.blas, sl.b, sl.r, n, s));
+    if ((e = fetch(1))) return e;
+    rn = std::sqrt(h[0].x);
+    double rel = rn / bn;
+    if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
+    std::vector<C> H((size_t)(m + 1) * m, 0.0), cv(m + 1, 0.0), yv(m, 0.0);
+    int steps = 0, cycles = 0, j0 = 0, status = rel <= c->tol ? DDQCD_OK : DDQCD_ERR_NOT_CONVERGED;
+    for (int cyc = 0; cyc < c->max_cycles && status != DDQCD_OK; cyc++) {
+        if (j0 == 0) {   // (re)start from the true residual
+            const double2 one = make_double2(1.0 / rn, 0), z0 = make_double2(0, 0);
+            HIPCHK(c, lincomb(Vc(0), sl.r, one, sl.r, z0, nullptr, z0, n, s));
+            std::fill(H.begin(), H.end(), C(0));
+            std::fill(cv.begin(), cv.end(), C(0));
+            cv[0] = rn;
+        }
+        int jend = m;
+        for (int j = j0; j < m; j++) {
+            {
+                Timer t(clk, &tsap);
+                if ((e = run_sap({y}, {Vc(j)}, {Zc(j)}, {1}, s))) return e;
+            }
+            {
+                Timer t(clk, &tA);
+                if ((e = apply_A64(c, Zc(j), Vc(j + 1), s))) return e;
+            }
+            double wn2;
+            {
+                Timer t(clk, &tgs);
+                double2 *w = Vc(j + 1);
+                double before;
+                std::vector<C> hsum(j + 1, 0.0);
+                // first pass; <w, w> in the same multi-dot where the column fits
+                const bool joint = j + 2 <= BLAS_MAXK;
+                HIPCHK(c, multidot(sl.blas, Vb, n, joint ? j + 2 : j + 1, w, n, s));
+                if ((e = fetch(joint ? j + 2 : j + 1))) return e;
+                std::vector<C> coef(j + 1);
+                for (int i = 0; i <= j; i++) coef[i] = C(h[i].x, h[i].y);
+                if (joint) before = h[j + 1].x;
+                else {
+                    HIPCHK(c, norm2(sl.blas, w, n, s));
+                    if ((e = fetch(1))) return e;
+                    before = h[0].x;
+                }
+                for (int pass = 0; pass < 2; pass++) {
+                    for (int i = 0; i <= j; i++) hsum[i] += coef[i];
+                    if ((e = put(coef, sl.blas.coef))) return e;
+                    HIPCHK(c, cgs_update(sl.blas, w, Vb, n, j + 1, w, n, s));
+                    if ((e = fetch(1))) return e;
+                    wn2 = h[0].x;
+                    if (pass == 1 || wn2 > 0.25 * before) break;
+                    before = wn2;
+                    HIPCHK(c, multidot(sl.blas, Vb, n, j + 1, w, n, s));
+                    if ((e = fetch(j + 1))) return e;
+                    for (int i = 0; i <= j; i++) coef[i] = C(h[i].x, h[i].y);
+                }
+                const double hn = std::sqrt(wn2);
+                if (!(hn > 0) || !std::isfinite(hn))
+                    return fail(c, DDQCD_ERR_NONFINITE, "breakdown: A M v vanished or is non-finite");
+                for (int i = 0; i <= j; i++) H[(size_t)i * m + j] = hsum[i];
+                H[(size_t)(j + 1) * m + j] = hn;
+                const double2 inv = make_double2(1.0 / hn, 0), z0 = make_double2(0, 0);
+                HIPCHK(c, lincomb(w, w, inv, w, z0, nullptr, z0, n, s));
+            }
+            steps++;
+            const double est = lsq_mgs(j + 2, j + 1, H.data(), m, cv.data(), yv.data()) / bn;
+            if (!std::isfinite(est)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual estimate");
+            if (est <= c->tol) {
+                jend = j + 1;
+                break;
+            }
+        }
+        {
+            Timer t(clk, &tother);
+            if ((e = put(std::vector<C>(yv.begin(), yv.begin() + jend), sl.blas.coef))) return e;
+            HIPCHK(c, axpy_multi(sl.blas, sl.x, Zb, n, jend, n, s));
+        }
+        {
+            Timer t(clk, &tA);
+            if ((e = apply_A64(c, sl.x, sl.r, s))) return e;
+        }
+        HIPCHK(c, residual(sl.blas, sl.b, sl.r, n, s));
+        if ((e = fetch(1))) return e;
+        rn = std::sqrt(h[0].x);
+        rel = rn / bn;
+        cycles++;
+        if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
+        if (rel <= c->tol) {
+            status = DDQCD_OK;
+            break;
+        }
+        if (k == 0 || jend < m) {
+            j0 = 0;
+            continue;
+        }
+        // deflated restart
+        Timer t(clk, &tother);
+        std::vector<C> sres(m + 1), Pk;
+        for (int i = 0; i <= m; i++) {
+            C tt = cv[i];
+            for (int j = 0; j < m; j++) tt -= H[(size_t)i * m + j] * yv[j];
+            sres[i] = tt;
+        }
+        if (!harmonic_ritz_basis(m, k, H, Pk)) {
+            j0 = 0;
+            continue;
+        }
+        const int k1 = k + 1;
+        std::vector<C> P((size_t)(m + 1) * k1, 0.0), Pz((size_t)m * k);
+        for (int i = 0; i < m; i++)
+            for (int q = 0; q < k; q++) P[(size_t)i * k1 + q] = Pz[(size_t)i * k + q] = Pk[(size_t)i * k + q];
+        for (int i = 0; i <= m; i++) P[(size_t)i * k1 + k] = sres[i];
+        for (int pass = 0; pass < 2; pass++)
+            for (int q = 0; q < k; q++) {
+                C d = 0;
+                for (int i = 0; i <= m; i++) d += std::conj(P[(size_t)i * k1 + q]) * P[(size_t)i * k1 + k];
+                for (int i = 0; i <= m; i++) P[(size_t)i * k1 + k] -= d * P[(size_t)i * k1 + q];
+            }
+        double pn = 0;
+        for (int i = 0; i <= m; i++) pn += std::norm(P[(size_t)i * k1 + k]);
+        pn = std::sqrt(pn);
+        for (int i = 0; i <= m; i++) P[(size_t)i * k1 + k] /= pn;
+        // V_{k+1} = V P and Z_k = Z P_k, formed in the spare columns, then moved
+        if ((e = put(P, sl.rcoef))) return e;
+        HIPCHK(c, recombine(Vb, n, m + 1, sl.rcoef, k1, Vc(m + 1), n, n, s));
+        HIPCHK(c, hipMemcpyAsync(Vc(0), Vc(m + 1), sizeof(double2) * n * k1, hipMemcpyDeviceToDevice, s));
+        if ((e = put(Pz, sl.rcoef))) return e;
+        HIPCHK(c, recombine(Zb, n, m, sl.rcoef, k, Zc(m), n, n, s));
+        HIPCHK(c, hipMemcpyAsync(Zc(0), Zc(m), sizeof(double2) * n * k, hipMemcpyDeviceToDevice, s));
+        // Hbar_k = P^H Hbar P_k, c = P^H s
+        std::vector<C> Hn((size_t)(m + 1) * m, 0.0);
+        for (int a = 0; a < k1; a++)
+            for (int q = 0; q < k; q++) {
+                C tt = 0;
+                for (int i = 0; i <= m; i++) {
+                    C hp = 0;
+                    for (int j = 0; j < m; j++) hp += H[(size_t)i * m + j] * Pk[(size_t)j * k + q];
+                    tt += std::conj(P[(size_t)i * k1 + a]) * hp;
+                }
+                Hn[(size_t)a * m + q] = tt;
+            }
+        H = Hn;
+        std::fill(cv.begin(), cv.end(), C(0));
+        for (int a = 0; a < k1; a++) {
+            C tt = 0;
+            for (int i = 0; i <= m; i++) tt += std::conj(P[(size_t)i * k1 + a]) * sres[i];
+            cv[a] = tt;
+        }
+        j0 = k;
+    }
+    clk.collect();
+    info.converged = status == DDQCD_OK;
+    info.iters = steps;
+    info.restarts = cycles;
+    info.rel_residual = rel;
+    info.t_sap_ms = tsap;
+    info.t_A_ms = tA;
+    info.t_gs_ms = tgs;
+    info.t_other_ms = tother;
+    if (status != DDQCD_OK) c->err = "not converged: relative residual " + std::to_string(rel);
+    return status;
+}
+
 // shared body of ddqcd_solve and ddqcd_solve_batch
 int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *const *b, int x_is_guess,
                   ddqcd_info *info, hipStream_t s)
@@ -895,7 +1285,17 @@ int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *c
         if (x_is_guess) HIPCHK(sys[i].c, import_spinor(g, x[i], sys[i].sl->x, P64, s));
     }
     std::vector<ddqcd_info> inf(sys.size());
-    const int st = fgcr(sys, std::vector<int>(sys.size(), x_is_guess != 0), inf, s);
+    int st = DDQCD_OK;
+    if (sys[0].c->outer == DDQCD_OUTER_FGMRES_DR) {
+        // one system after the other
+        for (size_t i = 0; i < sys.size(); i++) {
+            const int si = fgmres_dr(sys[i], x_is_guess != 0, inf[i], s);
+            if (si != DDQCD_OK && si != DDQCD_ERR_NOT_CONVERGED) return si;
+            if (si != DDQCD_OK) st = si;
+        }
+    } else {
+        st = fgcr(sys, std::vector<int>(sys.size(), x_is_guess != 0), inf, s);
+    }
     if (st != DDQCD_OK && st != DDQCD_ERR_NOT_CONVERGED) return st;
     for (size_t i = 0; i < sys.size(); i++) HIPCHK(sys[i].c, export_spinor(sys[i].c->g, sys[i].sl->x, P64, x[i], s));
     HIPCHK(sys[0].c, hipStreamSynchronize(s));
@@ -1029,7 +1429,8 @@ size_t ws_main_bytes(ddqcd_t c, int nrhs)
     gauge += 2 * (aligned(V * 36 * 16) + aligned(V * 36 * 8) + 2 * aligned(V * 36 * 4));   // clover, C_e / C_o^-1
     size_t slot = 4 * aligned(nc * 16) + 2 * aligned(half * 16) + aligned(faces * 16) + 2 * aligned((size_t)g.nd * 4);
     slot += aligned(sizeof(double2) * BLAS_NBLK * 32) + 2 * aligned(sizeof(double2) * 32);
-    slot += 2 * aligned(nc * 16 * std::max(c->restart, 5));                 // FGCR basis
+    slot += aligned(sizeof(double2) * RCOEF);
+    slot += 2 * aligned(nc * 16 * basis_columns(c));                        // outer solver basis
     slot += aligned(faces * 16) + aligned((size_t)g.nd * 4);                 // additive Schwarz
     return gauge + (size_t)nrhs * slot + 2 * aligned(nc * 8);               // + apply_D operands
 }
@@ -1188,10 +1589,26 @@ int ddqcd_set_workspace(ddqcd_t c, void *dev_ptr, size_t bytes)
     return DDQCD_OK;
 }
 
+int ddqcd_set_outer(ddqcd_t c, int kind, int deflate)
+{
+    if (!c) return DDQCD_ERR_ARG;
+    if (kind != DDQCD_OUTER_FGCR && kind != DDQCD_OUTER_FGMRES_DR) return fail(c, DDQCD_ERR_ARG, "bad outer solver");
+    if (kind == DDQCD_OUTER_FGCR && deflate != 0) return fail(c, DDQCD_ERR_ARG, "FGCR takes no deflation vectors");
+    if (deflate < 0 || (kind == DDQCD_OUTER_FGMRES_DR && deflate >= c->restart))
+        return fail(c, DDQCD_ERR_ARG, "deflation vectors must be in [0, restart)");
+    if (c->ws && !c->slots.empty())
+        return fail(c, DDQCD_ERR_STATE, "outer solver fixed once a workspace context has work slots");
+    c->outer = kind;
+    c->deflate = deflate;
+    return DDQCD_OK;
+}
+
 int ddqcd_set_solver(ddqcd_t c, int restart, double tol, int max_cycles)
 {
     if (!c) return DDQCD_ERR_ARG;
     if (restart < 1 || restart > BLAS_MAXK) return fail(c, DDQCD_ERR_ARG, "restart must be in [1, 16]");
+    if (c->outer == DDQCD_OUTER_FGMRES_DR && c->deflate >= restart)
+        return fail(c, DDQCD_ERR_ARG, "restart must exceed the deflation vectors");
     if (!(tol > 0) || !std::isfinite(tol) || max_cycles < 1) return fail(c, DDQCD_ERR_ARG, "bad tolerance or cycle limit");
     c->restart = restart;
     c->tol = tol;
@@ -1407,7 +1824,8 @@ int ddqcd_solve_batch(const ddqcd_t *ctxs, int n, double *const *x, const double
         int e = check_ready(c, "solve_batch");
         if (e) return e;
         if (c->restart != c0->restart || c->tol != c0->tol || c->max_cycles != c0->max_cycles ||
-            c->n_cycles != c0->n_cycles || c->schwarz != c0->schwarz)
+            c->n_cycles != c0->n_cycles || c->schwarz != c0->schwarz || c->outer != c0->outer ||
+            c->deflate != c0->deflate)
             return fail(c, DDQCD_ERR_ARG,
                         "batched contexts need equal solver settings, SAP cycle counts and Schwarz variant");
         const int k = used[c]++;

@@ -120,6 +120,10 @@ hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s
 // result[0] = (|v|^2, 0)
 hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s);
 hipError_t zero(double2 *v, long n, hipStream_t s);
+// out_q = sum_i W_i P[i][q], q < nq, i < nin (<= 24 each; P row-major on the
+// device; out must not overlap W)
+hipError_t recombine(const double2 *W, long ldw, int nin, const double2 *P, int nq, double2 *out, long ldo, long n,
+                     hipStream_t s);
 // result[0] = <t, s>, result[1] = (|t|^2, 0)
 hipError_t dot2(Blas &B, const double2 *t, const double2 *s_vec, long n, hipStream_t s);
 // out = ca a + cb b + cc c; c may be null; out may alias an input

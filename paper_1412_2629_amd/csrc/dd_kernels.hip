@@ -706,6 +706,47 @@ hipError_t lincomb(double2 *out, const double2 *a, double2 ca, const double2 *b,
     return hipGetLastError();
 }
 
+// out_q = sum_i W_i P[i][q] for q < nq (columns of n complex numbers, W_i =
+// W + i*ldw, out_q = out + q*ldo; P row-major nin x nq on the device, nin, nq
+// <= RECOMB_MAX).  Each element of the inputs is read once; the outputs of one
+// element accumulate in registers.
+constexpr int RECOMB_MAX = 24;
+__global__ __launch_bounds__(BS) void k_recombine(const double2 *W, long ldw, int nin, const double2 *P, int nq,
+                                                  double2 *out, long ldo, long n)
+{
+    __shared__ double2 sp[RECOMB_MAX * RECOMB_MAX];
+    for (int t = threadIdx.x; t < nin * nq; t += BS) sp[t] = P[t];
+    __syncthreads();
+    for (long e = (long)blockIdx.x * BS + threadIdx.x; e < n; e += (long)gridDim.x * BS) {
+        double2 acc[RECOMB_MAX];
+#pragma unroll
+        for (int q = 0; q < RECOMB_MAX; q++) acc[q] = make_double2(0, 0);
+        for (int i = 0; i < nin; i++) {
+            const double2 w = W[i * ldw + e];
+#pragma unroll
+            for (int q = 0; q < RECOMB_MAX; q++) {
+                if (q >= nq) break;
+                const double2 c = sp[i * nq + q];
+                acc[q].x += c.x * w.x - c.y * w.y;
+                acc[q].y += c.x * w.y + c.y * w.x;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RECOMB_MAX; q++) {
+            if (q >= nq) break;
+            out[q * ldo + e] = acc[q];
+        }
+    }
+}
+
+hipError_t recombine(const double2 *W, long ldw, int nin, const double2 *P, int nq, double2 *out, long ldo, long n,
+                     hipStream_t s)
+{
+    if (nin < 1 || nq < 1 || nin > RECOMB_MAX || nq > RECOMB_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_recombine, blas_blocks(n), BS, 0, s, W, ldw, nin, P, nq, out, ldo, n);
+    return hipGetLastError();
+}
+
 __global__ void k_zero(double2 *v, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)

@@ -18,7 +18,7 @@ PREC = {"f64": FP64, "f32": FP32, "f16": FP16, "bf16": BF16, FP64: FP64, FP32: F
 SCHED_SWEEPS, SCHED_QUEUE, SCHED_GRAPH = 0, 1, 2
 PRODUCT = {"lane": 0, "tile": 1, "mfma_f32": 2, "mfma_bf16": 3}
 
-EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_workspace_size", "ddqcd_set_workspace", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz",
+EXPORTS = ["ddqcd_create", "ddqcd_destroy", "ddqcd_workspace_size", "ddqcd_set_workspace", "ddqcd_set_sap", "ddqcd_set_schedule", "ddqcd_set_schwarz", "ddqcd_set_outer",
            "ddqcd_set_solver", "ddqcd_load_gauge",
            "ddqcd_apply_D", "ddqcd_sap", "ddqcd_sap_noalloc", "ddqcd_solve", "ddqcd_solve_batch", "ddqcd_solve_bicgstab", "ddqcd_tune_domain",
            "ddqcd_tune_sap",
@@ -59,6 +59,7 @@ def lib():
         L.ddqcd_set_solver.argtypes = [vp, i, d, i]
         L.ddqcd_set_schedule.argtypes = [vp, i]
         L.ddqcd_set_schwarz.argtypes = [vp, i]
+        L.ddqcd_set_outer.argtypes = [vp, i, i]
         L.ddqcd_load_gauge.argtypes = [vp, vp, vp]
         L.ddqcd_apply_D.argtypes = [vp, vp, vp, i, i, vp]
         L.ddqcd_sap.argtypes = [vp, vp, vp, i, vp]
@@ -164,6 +165,12 @@ class Context:
         """"multiplicative" (the default) or "additive" Schwarz preconditioner."""
         mode = {"multiplicative": 0, "additive": 1}.get(kind, kind)
         self._check(lib().ddqcd_set_schwarz(self._h, mode), "set_schwarz")
+
+    def set_outer(self, kind="fgcr", deflate=0):
+        """"fgcr" (the default) or "fgmres_dr" with `deflate` deflation vectors
+        (the basis size is the restart of set_solver)."""
+        mode = {"fgcr": 0, "fgmres_dr": 1}.get(kind, kind)
+        self._check(lib().ddqcd_set_outer(self._h, mode, deflate), "set_outer")
 
     def set_solver(self, restart=16, tol=1e-10, max_cycles=64):
         self._check(lib().ddqcd_set_solver(self._h, restart, ctypes.c_double(tol), max_cycles), "set_solver")

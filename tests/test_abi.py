@@ -77,6 +77,12 @@ def test_create_settings_and_state_errors():
         assert L.ddqcd_set_solver(h, 16, 0.0, 10) == ddqcd.ERR_ARG
         assert L.ddqcd_set_solver(h, 16, 1e-10, 0) == ddqcd.ERR_ARG
         assert L.ddqcd_set_solver(h, 8, 1e-10, 10) == ddqcd.OK
+        assert L.ddqcd_set_outer(h, 2, 0) == ddqcd.ERR_ARG           # no such solver
+        assert L.ddqcd_set_outer(h, 0, 3) == ddqcd.ERR_ARG           # FGCR has no deflation
+        assert L.ddqcd_set_outer(h, 1, 8) == ddqcd.ERR_ARG           # deflation >= basis size
+        assert L.ddqcd_set_outer(h, 1, 4) == ddqcd.OK
+        assert L.ddqcd_set_solver(h, 4, 1e-10, 10) == ddqcd.ERR_ARG  # basis no larger than the deflation
+        assert L.ddqcd_set_outer(h, 0, 0) == ddqcd.OK
         dummy = ctypes.c_void_p(4096)
         dummy2 = ctypes.c_void_p(8192)
         # no gauge field loaded yet: rejected before any device work

@@ -390,3 +390,62 @@ def test_tile_graph_batch_and_rejects():
         with pytest.raises(ddqcd.DDQCDError) as e:
             c.set_sap(4, 5, bad[1], "mfma_f32")
         assert e.value.status == ddqcd.ERR_GEOMETRY
+
+
+# ---------------------------------------------------------------------------
+# flexible GMRES with deflated restarts (the paper's outer solver)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[1], SMALL[3]], ids=repr)
+@pytest.mark.parametrize("prec", ["f64", "f16"])
+@pytest.mark.parametrize("m,k", [(8, 4), (16, 6), (6, 0)])
+def test_solve_fgmres_dr(case, prec, m, k, oracle):
+    """Solution and true residual against the oracle; the FP64 path takes the
+    oracle's FGMRES-DR step count."""
+    f = case.source(30)
+    x_or, st, steps_or, _ = oracle.fgmres_dr(case.L, case.b, BC, case.U, case.C, case.Ci, f, m, k,
+                                             n_cycles=case.n_cycles, n_mr=case.n_mr, tol=1e-10)
+    assert st == 0
+    ctx = case.context(prec)
+    ctx.set_solver(m, 1e-10, 64)
+    ctx.set_outer("fgmres_dr", k)
+    x, info, status = ctx.solve(dev(f))
+    x = host(x)
+    true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+    x_ex, st_ex, _, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                    n_mr=case.n_mr, restart=16, tol=1e-12)
+    err = rel(x, x_ex)
+    print(f"{case} {prec} FGMRES-DR({m},{k}): steps {info[0]['iters']} in {info[0]['restarts']} cycles "
+          f"(oracle fp64 {steps_or}), true residual {true_res:.2e}, solution error {err:.2e}")
+    assert status == 0 and true_res <= 1e-10 and err <= 1e-8
+    assert abs(info[0]["rel_residual"] - true_res) <= 1e-12
+    if prec == "f64":
+        assert info[0]["iters"] == steps_or
+
+
+def test_fgmres_dr_multi_rhs_batch_and_settings(oracle):
+    """Several right-hand sides and a batch (solved one after the other), a
+    converged guess takes no step, bad settings are refused."""
+    from paper_1412_2629_amd import ddqcd
+    case = SMALL[2]
+    ctx = case.context("f32")
+    ctx.set_solver(8, 1e-10, 64)
+    ctx.set_outer("fgmres_dr", 4)
+    fs = np.stack([case.source(31), case.source(32)])
+    x, info, st = ctx.solve(dev(fs))
+    assert st == 0
+    for q in range(2):
+        assert rel(oracle.apply_A(case.L, BC, case.U, case.C, host(x)[q]), fs[q]) <= 1e-10
+    x2, info2, st2 = ctx.solve(dev(fs), x0=x)
+    assert st2 == 0 and all(i["iters"] == 0 for i in info2)
+    other = SMALL[3].context("f32")
+    other.set_solver(8, 1e-10, 64)
+    with pytest.raises(ddqcd.DDQCDError) as e:     # outer solvers differ
+        ddqcd.solve_batch([ctx, other], [dev(fs[0]), dev(SMALL[3].source(33))])
+    assert e.value.status == ddqcd.ERR_ARG
+    other.set_outer("fgmres_dr", 4)
+    xs, infos, st3 = ddqcd.solve_batch([ctx, other], [dev(fs[0]), dev(SMALL[3].source(33))])
+    assert st3 == 0 and np.array_equal(host(xs[0]), host(x)[0])
+    for k in (8, -1):                              # deflation vectors outside [0, basis size)
+        with pytest.raises(ddqcd.DDQCDError):
+            ctx.set_outer("fgmres_dr", k)
