@@ -185,11 +185,17 @@ int ddqcd_set_workspace(ddqcd_t ctx, void *dev_ptr, size_t bytes);
  * kept at each restart (0 <= k < m; the paper uses m = 8, k = 4 and m = 16,
  * k = 6, Sec. IV-C), right-hand sides one after the other.  Both keep the
  * orthogonalisation, residuals and solution update in FP64 and stop on the
- * true residual recomputed at each cycle's end.  ddqcd_solve_batch needs equal
+ * true residual recomputed at each cycle's end.  DDQCD_OUTER_FGCR_MIXED
+ * (deflate 0): the mixed-precision outer solver of Sec. VI: FP64 iterative
+ * refinement (true residual r = b - A x, x += |r| e) around FGCR cycles in FP32
+ * (vectors, operator with two-row links, Gram-Schmidt with FP64 accumulation)
+ * that reduce their residual by 1e-5 each (or to what the tolerance needs),
+ * with the SAP preconditioner reading and writing FP32; needs a
+ * reduced-precision preconditioner; right-hand sides one after the other.  ddqcd_solve_batch needs equal
  * settings on all contexts.  DDQCD_ERR_ARG for values out of range,
  * DDQCD_ERR_STATE on a workspace context that already has work slots (their
  * basis size is fixed). */
-typedef enum { DDQCD_OUTER_FGCR = 0, DDQCD_OUTER_FGMRES_DR = 1 } ddqcd_outer;
+typedef enum { DDQCD_OUTER_FGCR = 0, DDQCD_OUTER_FGMRES_DR = 1, DDQCD_OUTER_FGCR_MIXED = 2 } ddqcd_outer;
 int ddqcd_set_outer(ddqcd_t ctx, int kind, int deflate);
 
 /* Outer solver settings: restart >= 1 basis vectors per cycle, tol > 0 on the

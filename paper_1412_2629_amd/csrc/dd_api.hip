@@ -491,7 +491,7 @@ int capture_graph(ddqcd_t lead, Plan &plan, int n_cycles)
 // on[i] == 0 are left out (their out_i is not written).  All systems share the
 // SAP cycle count.
 int run_sap(const std::vector<Sys> &all, const std::vector<const double2 *> &eta_all,
-            const std::vector<double2 *> &out_all, const std::vector<int> &on, hipStream_t s)
+            const std::vector<double2 *> &out_all, const std::vector<int> &on, hipStream_t s, bool io32 = false)
 {
     std::vector<Sys> sys;
     std::vector<const double2 *> eta;
@@ -535,6 +535,7 @@ int run_sap(const std::vector<Sys> &all, const std::vector<const double2 *> &eta
         a.links = links_for(c, c->sap_prec);
         a.cs = schur_for(c, c->sap_prec);
         a.active = 1;
+        a.io32 = io32;
     }
     HIPCHK(lead, hipMemcpyAsync(plan->d_args, plan->h_args.data(), sizeof(SapArgs) * sys.size(),
                                 hipMemcpyHostToDevice, s));
@@ -1274,6 +1275,148 @@ int fgmres_dr(const Sys &y, bool guess, ddqcd_info &info, hipStream_t s)
     return status;
 }
 
+// ---- mixed-precision outer solver (iterative refinement) ------------------------
+//
+// Solves A x = b for one system by FP64 iterative refinement around an FP32
+// flexible GCR: each outer step takes the true residual r = b - A x in FP64,
+// solves A e = r / |r| by one FGCR cycle whose vectors, operator (two-row FP32
+// links, FP32 clover) and Gram-Schmidt are FP32 (dot products accumulated in
+// FP64), preconditioned by the context's SAP reading and writing FP32
+// vectors, until its residual has fallen by MIXED_INNER_REDUCTION (or below
+// what the outer tolerance needs), and adds |r| e to x in FP64.
+constexpr double MIXED_INNER_REDUCTION = 1e-5;
+
+int fgcr_mixed(const Sys &y, bool guess, ddqcd_info &info, hipStream_t s)
+{
+    ddqcd_t c = y.c;
+    Slot &sl = *y.sl;
+    const int m = c->restart;
+    const long n = ncomplex(c->g);
+    int e;
+    if ((e = ensure_basis(c, sl))) return e;
+    // FP32 work vectors in the FP64 basis arrays: Z32 (m columns) in Z, W32 (m)
+    // and r32 in W (each FP64 column holds two FP32 ones)
+    float2 *Z32 = (float2 *)sl.Z, *W32 = (float2 *)sl.W, *r32 = W32 + (long)m * n;
+    double tsap = 0, tA = 0, tgs = 0, tother = 0;
+    Clock clk(s);
+    double2 h[32];
+    auto fetch = [&](int cnt) -> int {
+        HIPCHK(c, hipMemcpyAsync(h, sl.blas.result, sizeof(double2) * cnt, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return DDQCD_OK;
+    };
+    auto put = [&](const std::vector<C> &v) -> int {
+        HIPCHK(c, hipMemcpyAsync(sl.blas.coef, v.data(), sizeof(double2) * v.size(), hipMemcpyHostToDevice, s));
+        return DDQCD_OK;
+    };
+    info = ddqcd_info{};
+    if (!guess) HIPCHK(c, zero(sl.x, n, s));
+    HIPCHK(c, norm2(sl.blas, sl.b, n, s));
+    if ((e = fetch(1))) return e;
+    const double bn = std::sqrt(h[0].x);
+    if (!std::isfinite(bn)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite right-hand side");
+    if (bn == 0) {
+        HIPCHK(c, zero(sl.x, n, s));
+        info.converged = 1;
+        return DDQCD_OK;
+    }
+    const void *U32 = links_for(c, DDQCD_FP32), *C32 = clover_for(c, DDQCD_FP32);
+    std::vector<C> a((size_t)m * m), cc(m), alpha(m);
+    std::vector<double> bb(m);
+    int steps = 0, outer = 0, status = DDQCD_ERR_NOT_CONVERGED;
+    double rel = 0;
+    for (;;) {
+        {
+            Timer t(clk, &tA);
+            if ((e = apply_A64(c, sl.x, sl.r, s))) return e;
+        }
+        HIPCHK(c, residual(sl.blas, sl.b, sl.r, n, s));
+        if ((e = fetch(1))) return e;
+        const double rn = std::sqrt(h[0].x);
+        rel = rn / bn;
+        if (!std::isfinite(rel)) return fail(c, DDQCD_ERR_NONFINITE, "non-finite residual");
+        if (rel <= c->tol) {
+            status = DDQCD_OK;
+            break;
+        }
+        if (outer >= c->max_cycles) break;
+        outer++;
+        HIPCHK(c, to_f32(sl.r, 1.0 / rn, r32, n, s));
+        const double target = std::max(MIXED_INNER_REDUCTION, 0.5 * c->tol / rel);
+        int kend = 0;
+        std::fill(a.begin(), a.end(), C(0));
+        for (int k = 0; k < m; k++) {
+            float2 *zk = Z32 + (long)k * n, *wk = W32 + (long)k * n;
+            {
+                Timer t(clk, &tsap);
+                if ((e = run_sap({y}, {(const double2 *)r32}, {(double2 *)zk}, {1}, s, true))) return e;
+            }
+            {
+                Timer t(clk, &tA);
+                HIPCHK(c, apply_A(c->g, zk, wk, U32, C32, P32, s));
+            }
+            Timer t(clk, &tgs);
+            double before = 0, wn2 = 0;
+            if (k > 0) {
+                HIPCHK(c, multidot32(sl.blas, W32, n, k + 1, wk, n, s));   // column k is w itself
+                if ((e = fetch(k + 1))) return e;
+                before = h[k].x;
+                for (int pass = 0; pass < 2; pass++) {
+                    std::vector<C> coef(k);
+                    for (int j = 0; j < k; j++) {
+                        coef[j] = C(h[j].x, h[j].y);
+                        a[(size_t)j * m + k] += coef[j];
+                    }
+                    if ((e = put(coef))) return e;
+                    HIPCHK(c, cgs_update32(sl.blas, wk, W32, n, k, n, s));
+                    if ((e = fetch(1))) return e;
+                    wn2 = h[0].x;
+                    if (pass == 1 || wn2 > 0.25 * before) break;
+                    before = wn2;
+                    HIPCHK(c, multidot32(sl.blas, W32, n, k, wk, n, s));
+                    if ((e = fetch(k))) return e;
+                }
+            } else {
+                HIPCHK(c, multidot32(sl.blas, wk, n, 1, wk, n, s));
+                if ((e = fetch(1))) return e;
+                wn2 = h[0].x;
+            }
+            bb[k] = std::sqrt(wn2);
+            if (!(bb[k] > 0) || !std::isfinite(bb[k]))
+                return fail(c, DDQCD_ERR_NONFINITE, "breakdown: A M r vanished or is non-finite");
+            HIPCHK(c, scale_dot32(sl.blas, wk, 1.0 / bb[k], r32, n, s));
+            if ((e = fetch(1))) return e;
+            cc[k] = C(h[0].x, h[0].y);
+            HIPCHK(c, axpy32(sl.blas, r32, make_double2(cc[k].real(), cc[k].imag()), wk, n, s));
+            if ((e = fetch(1))) return e;
+            steps++;
+            kend = k + 1;
+            if (std::sqrt(h[0].x) <= target) break;
+        }
+        {
+            Timer t(clk, &tother);
+            for (int k = kend - 1; k >= 0; k--) {
+                C sum = cc[k];
+                for (int j = k + 1; j < kend; j++) sum -= a[(size_t)k * m + j] * alpha[j];
+                alpha[k] = sum / bb[k];
+            }
+            if ((e = put(std::vector<C>(alpha.begin(), alpha.begin() + kend)))) return e;
+            HIPCHK(c, axpy_mixed(sl.blas, sl.x, Z32, n, kend, rn, n, s));
+        }
+    }
+    clk.collect();
+    info.converged = status == DDQCD_OK;
+    info.iters = steps;
+    info.restarts = outer;
+    info.rel_residual = rel;
+    info.t_sap_ms = tsap;
+    info.t_A_ms = tA;
+    info.t_gs_ms = tgs;
+    info.t_other_ms = tother;
+    if (status != DDQCD_OK) c->err = "not converged: relative residual " + std::to_string(rel);
+    return status;
+}
+
 // shared body of ddqcd_solve and ddqcd_solve_batch
 int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *const *b, int x_is_guess,
                   ddqcd_info *info, hipStream_t s)
@@ -1286,10 +1429,11 @@ int solve_systems(const std::vector<Sys> &sys, double *const *x, const double *c
     }
     std::vector<ddqcd_info> inf(sys.size());
     int st = DDQCD_OK;
-    if (sys[0].c->outer == DDQCD_OUTER_FGMRES_DR) {
+    if (sys[0].c->outer != DDQCD_OUTER_FGCR) {
         // one system after the other
         for (size_t i = 0; i < sys.size(); i++) {
-            const int si = fgmres_dr(sys[i], x_is_guess != 0, inf[i], s);
+            const int si = sys[0].c->outer == DDQCD_OUTER_FGMRES_DR ? fgmres_dr(sys[i], x_is_guess != 0, inf[i], s)
+                                                                     : fgcr_mixed(sys[i], x_is_guess != 0, inf[i], s);
             if (si != DDQCD_OK && si != DDQCD_ERR_NOT_CONVERGED) return si;
             if (si != DDQCD_OK) st = si;
         }
@@ -1529,6 +1673,8 @@ int ddqcd_set_sap(ddqcd_t c, int n_cycles, int n_mr, int prec, int product)
     if (!sap_product_supported(c->g.b, prec, product))
         return fail(c, DDQCD_ERR_GEOMETRY, "the right-hand-side tile forms need 4x4x4x4 domains and FP16 or BF16 "
                                            "storage");
+    if (prec == DDQCD_FP64 && c->outer == DDQCD_OUTER_FGCR_MIXED)
+        return fail(c, DDQCD_ERR_ARG, "the mixed-precision outer solver needs a reduced-precision preconditioner");
     c->n_cycles = n_cycles;
     c->n_mr = n_mr;
     c->sap_prec = prec;
@@ -1592,8 +1738,11 @@ int ddqcd_set_workspace(ddqcd_t c, void *dev_ptr, size_t bytes)
 int ddqcd_set_outer(ddqcd_t c, int kind, int deflate)
 {
     if (!c) return DDQCD_ERR_ARG;
-    if (kind != DDQCD_OUTER_FGCR && kind != DDQCD_OUTER_FGMRES_DR) return fail(c, DDQCD_ERR_ARG, "bad outer solver");
-    if (kind == DDQCD_OUTER_FGCR && deflate != 0) return fail(c, DDQCD_ERR_ARG, "FGCR takes no deflation vectors");
+    if (kind != DDQCD_OUTER_FGCR && kind != DDQCD_OUTER_FGMRES_DR && kind != DDQCD_OUTER_FGCR_MIXED)
+        return fail(c, DDQCD_ERR_ARG, "bad outer solver");
+    if (kind != DDQCD_OUTER_FGMRES_DR && deflate != 0) return fail(c, DDQCD_ERR_ARG, "FGCR takes no deflation vectors");
+    if (kind == DDQCD_OUTER_FGCR_MIXED && c->sap_prec == DDQCD_FP64)
+        return fail(c, DDQCD_ERR_ARG, "the mixed-precision outer solver needs a reduced-precision preconditioner");
     if (deflate < 0 || (kind == DDQCD_OUTER_FGMRES_DR && deflate >= c->restart))
         return fail(c, DDQCD_ERR_ARG, "deflation vectors must be in [0, restart)");
     if (c->ws && !c->slots.empty())

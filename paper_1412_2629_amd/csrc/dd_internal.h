@@ -64,6 +64,7 @@ struct SapArgs {
     const void *cs;     // C_e on even / C_o^-1 on odd sites [d][36][Vd]
     void *rho_tmp;      // odd-site right-hand sides [d][12][Vd/2] when not kept in LDS
     int active;         // 0: skip this system (already converged)
+    int io32;           // eta and out are FP32 (float2) vectors (FP32/FP16/BF16 block solves only)
 };
 bool sap_shape_supported(const int b[4]);
 bool sap_prec_supported(const int b[4], int prec);
@@ -120,6 +121,16 @@ hipError_t residual(Blas &B, const double2 *b, double2 *r, long n, hipStream_t s
 // result[0] = (|v|^2, 0)
 hipError_t norm2(Blas &B, const double2 *v, long n, hipStream_t s);
 hipError_t zero(double2 *v, long n, hipStream_t s);
+// FP32 vectors, FP64 accumulation: result[j] = <W_j, v> (k <= 16);
+// w -= sum_j coef[j] W_j with result[0] = |w|^2; w *= inv_b with result[0] =
+// <w, r>; r -= c w with result[0] = |r|^2; x (FP64) += scale sum_j coef[j] Z_j;
+// out = sc * in rounded to FP32
+hipError_t multidot32(Blas &B, const float2 *W, long ldw, int k, const float2 *v, long n, hipStream_t s);
+hipError_t cgs_update32(Blas &B, float2 *w, const float2 *W, long ldw, int k, long n, hipStream_t s);
+hipError_t scale_dot32(Blas &B, float2 *w, double inv_b, const float2 *r, long n, hipStream_t s);
+hipError_t axpy32(Blas &B, float2 *r, double2 c, const float2 *w, long n, hipStream_t s);
+hipError_t axpy_mixed(Blas &B, double2 *x, const float2 *Z, long ldz, int k, double scale, long n, hipStream_t s);
+hipError_t to_f32(const double2 *in, double sc, float2 *out, long n, hipStream_t s);
 // out_q = sum_i W_i P[i][q], q < nq, i < nin (<= 24 each; P row-major on the
 // device; out must not overlap W)
 hipError_t recombine(const double2 *W, long ldw, int nin, const double2 *P, int nq, double2 *out, long ldo, long n,

@@ -706,6 +706,167 @@ hipError_t lincomb(double2 *out, const double2 *a, double2 ca, const double2 *b,
     return hipGetLastError();
 }
 
+// ---- FP32 vectors with FP64 accumulation (the inner solve of the
+// mixed-precision outer solver) ----------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(BS) void k_multidot32(const float2 *W, long ldw, const float2 *v, long n, double2 *partial)
+{
+    double acc[2 * K];
+#pragma unroll
+    for (int q = 0; q < 2 * K; q++) acc[q] = 0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const float2 b = v[i];
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const float2 a = W[j * ldw + i];
+            acc[2 * j] += (double)a.x * b.x + (double)a.y * b.y;
+            acc[2 * j + 1] += (double)a.x * b.y - (double)a.y * b.x;
+        }
+    }
+    block_reduce_store<2 * K>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t multidot32(Blas &B, const float2 *W, long ldw, int k, const float2 *v, long n, hipStream_t s)
+{
+    switch (k) {
+#define MD(K) case K: hipLaunchKernelGGL(k_multidot32<K>, blas_blocks(n), BS, 0, s, W, ldw, v, n, B.partial); break;
+        MD(1) MD(2) MD(3) MD(4) MD(5) MD(6) MD(7) MD(8) MD(9) MD(10) MD(11) MD(12) MD(13) MD(14) MD(15) MD(16)
+#undef MD
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), k, B.result);
+    return hipGetLastError();
+}
+
+template <int K>
+__global__ __launch_bounds__(BS) void k_cgs_update32(float2 *w, const float2 *W, long ldw, const double2 *coef, long n,
+                                                     double2 *partial)
+{
+    double2 c[K > 0 ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; j++) c[j] = coef[j];
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const float2 x0 = w[i];
+        double xr = x0.x, xi = x0.y;
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const float2 a = W[j * ldw + i];
+            xr -= c[j].x * a.x - c[j].y * a.y;
+            xi -= c[j].x * a.y + c[j].y * a.x;
+        }
+        const float2 x = make_float2((float)xr, (float)xi);
+        w[i] = x;
+        acc[0] += (double)x.x * x.x + (double)x.y * x.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t cgs_update32(Blas &B, float2 *w, const float2 *W, long ldw, int k, long n, hipStream_t s)
+{
+    switch (k) {
+#define CU(K) case K: hipLaunchKernelGGL(k_cgs_update32<K>, blas_blocks(n), BS, 0, s, w, W, ldw, B.coef, n, B.partial); break;
+        CU(0) CU(1) CU(2) CU(3) CU(4) CU(5) CU(6) CU(7) CU(8) CU(9) CU(10) CU(11) CU(12) CU(13) CU(14) CU(15) CU(16)
+#undef CU
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
+    return hipGetLastError();
+}
+
+// w *= inv_b; then result[0] = <w, r>, after which r -= c w with c = that dot
+// is left to k_axpy32 (c is only known on the host)
+__global__ __launch_bounds__(BS) void k_scale_dot32(float2 *w, double inv_b, const float2 *r, long n, double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        float2 x = w[i];
+        x.x = (float)(x.x * inv_b);
+        x.y = (float)(x.y * inv_b);
+        w[i] = x;
+        const float2 b = r[i];
+        acc[0] += (double)x.x * b.x + (double)x.y * b.y;
+        acc[1] += (double)x.x * b.y - (double)x.y * b.x;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t scale_dot32(Blas &B, float2 *w, double inv_b, const float2 *r, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_dot32, blas_blocks(n), BS, 0, s, w, inv_b, r, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
+    return hipGetLastError();
+}
+
+// r -= c w; result[0] = (|r|^2, 0)
+__global__ __launch_bounds__(BS) void k_axpy32(float2 *r, double2 c, const float2 *w, long n, double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const float2 x = w[i];
+        float2 y = r[i];
+        y.x = (float)(y.x - (c.x * x.x - c.y * x.y));
+        y.y = (float)(y.y - (c.x * x.y + c.y * x.x));
+        r[i] = y;
+        acc[0] += (double)y.x * y.x + (double)y.y * y.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t axpy32(Blas &B, float2 *r, double2 c, const float2 *w, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy32, blas_blocks(n), BS, 0, s, r, c, w, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
+    return hipGetLastError();
+}
+
+// x += scale * sum_j coef[j] Z_j (FP64 x, FP32 Z)
+template <int K>
+__global__ __launch_bounds__(BS) void k_axpy_mixed(double2 *x, const float2 *Z, long ldz, const double2 *coef,
+                                                   double scale, long n)
+{
+    double2 c[K];
+#pragma unroll
+    for (int j = 0; j < K; j++) c[j] = make_double2(scale * coef[j].x, scale * coef[j].y);
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        double2 y = x[i];
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            const float2 a = Z[j * ldz + i];
+            y.x += c[j].x * a.x - c[j].y * a.y;
+            y.y += c[j].x * a.y + c[j].y * a.x;
+        }
+        x[i] = y;
+    }
+}
+
+hipError_t axpy_mixed(Blas &B, double2 *x, const float2 *Z, long ldz, int k, double scale, long n, hipStream_t s)
+{
+    switch (k) {
+#define AX(K) case K: hipLaunchKernelGGL(k_axpy_mixed<K>, blas_blocks(n), BS, 0, s, x, Z, ldz, B.coef, scale, n); break;
+        AX(1) AX(2) AX(3) AX(4) AX(5) AX(6) AX(7) AX(8) AX(9) AX(10) AX(11) AX(12) AX(13) AX(14) AX(15) AX(16)
+#undef AX
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// out = s * in, rounded to FP32
+__global__ __launch_bounds__(BS) void k_to_f32(const double2 *in, double sc, float2 *out, long n)
+{
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const double2 v = in[i];
+        out[i] = make_float2((float)(sc * v.x), (float)(sc * v.y));
+    }
+}
+
+hipError_t to_f32(const double2 *in, double sc, float2 *out, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f32, blas_blocks(n), BS, 0, s, in, sc, out, n);
+    return hipGetLastError();
+}
+
 // out_q = sum_i W_i P[i][q] for q < nq (columns of n complex numbers, W_i =
 // W + i*ldw, out_q = out + q*ldo; P row-major nin x nq on the device, nin, nq
 // <= RECOMB_MAX).  Each element of the inputs is read once; the outputs of one

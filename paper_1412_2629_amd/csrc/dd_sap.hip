@@ -815,8 +815,13 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
         for (int k = 0; k < 12; k++) A[k] = czero<T>();
     } else if (f.first) {
+        if (a.io32) {
 #pragma unroll
-        for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
+            for (int k = 0; k < 12; k++) A[k] = ld<T, float>((const float2 *)a.eta, sbase + (long)k * VD);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; k++) A[k] = ld<T, double>(a.eta, sbase + (long)k * VD);
+        }
     } else if (par == 0) {
         T sc = SCALED ? T(a.res_scale[d]) : T(1);
         const v2<SS> *res = (const v2<SS> *)a.res;
@@ -935,7 +940,8 @@ __device__ __forceinline__ void lds_block_solve(const SapArgs &a, const int d, c
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             cx<T> ps = f.first ? A[k] : ld<T, PS>(psi_in, sbase + (long)k * VD) + A[k];
-            if (f.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
+            if (f.last && a.io32) st<T, float>((float2 *)a.out, sbase + (long)k * VD, ps);
+            else if (f.last) st<T, double>(a.out, sbase + (long)k * VD, ps);
             else st<T, PS>(psi_out, sbase + (long)k * VD, ps);
         }
     }
@@ -1504,6 +1510,12 @@ __global__ __launch_bounds__(Sh::VH * RT) void k_sap_tile(const SapArgs *args, c
     if (!live) {
 #pragma unroll
         for (int k = 0; k < 12; k++) Ae[k] = Ao[k] = czero<T>();
+    } else if (v.first && a.io32) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            Ae[k] = ld<T, float>((const float2 *)a.eta, se + (long)k * VD);
+            Ao[k] = ld<T, float>((const float2 *)a.eta, so + (long)k * VD);
+        }
     } else if (v.first) {
 #pragma unroll
         for (int k = 0; k < 12; k++) {
@@ -1621,7 +1633,8 @@ __global__ __launch_bounds__(Sh::VH * RT) void k_sap_tile(const SapArgs *args, c
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 const cx<T> ps = v.first ? A[k] : ld<T, PS>(psi_in, sb + (long)k * VD) + A[k];
-                if (v.last) st<T, double>(a.out, sb + (long)k * VD, ps);
+                if (v.last && a.io32) st<T, float>((float2 *)a.out, sb + (long)k * VD, ps);
+                else if (v.last) st<T, double>(a.out, sb + (long)k * VD, ps);
                 else st<T, PS>(psi_out, sb + (long)k * VD, ps);
             }
         }

@@ -167,9 +167,10 @@ class Context:
         self._check(lib().ddqcd_set_schwarz(self._h, mode), "set_schwarz")
 
     def set_outer(self, kind="fgcr", deflate=0):
-        """"fgcr" (the default) or "fgmres_dr" with `deflate` deflation vectors
-        (the basis size is the restart of set_solver)."""
-        mode = {"fgcr": 0, "fgmres_dr": 1}.get(kind, kind)
+        """"fgcr" (the default), "fgmres_dr" with `deflate` deflation vectors
+        (the basis size is the restart of set_solver) or "fgcr_mixed" (FP64
+        iterative refinement around FP32 FGCR cycles)."""
+        mode = {"fgcr": 0, "fgmres_dr": 1, "fgcr_mixed": 2}.get(kind, kind)
         self._check(lib().ddqcd_set_outer(self._h, mode, deflate), "set_outer")
 
     def set_solver(self, restart=16, tol=1e-10, max_cycles=64):

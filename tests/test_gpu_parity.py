@@ -449,3 +449,38 @@ def test_fgmres_dr_multi_rhs_batch_and_settings(oracle):
     for k in (8, -1):                              # deflation vectors outside [0, basis size)
         with pytest.raises(ddqcd.DDQCDError):
             ctx.set_outer("fgmres_dr", k)
+
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[1], SMALL[3], SMALL[5]], ids=repr)
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_solve_mixed_outer(case, prec, oracle):
+    """The mixed-precision outer solver (FP64 refinement around FP32 FGCR
+    cycles): true residual and solution against the oracle."""
+    f = case.source(40)
+    x_ex, st, _, _ = oracle.fgcr(case.L, case.b, BC, case.U, case.C, case.Ci, f, n_cycles=case.n_cycles,
+                                 n_mr=case.n_mr, restart=16, tol=1e-12)
+    assert st == 0
+    ctx = case.context(prec)
+    ctx.set_solver(16, 1e-10, 64)
+    ctx.set_outer("fgcr_mixed")
+    x, info, status = ctx.solve(dev(f))
+    x = host(x)
+    true_res = rel(oracle.apply_A(case.L, BC, case.U, case.C, x), f)
+    err = rel(x, x_ex)
+    print(f"{case} {prec} mixed outer: {info[0]['iters']} steps in {info[0]['restarts']} refinements, true residual "
+          f"{true_res:.2e}, solution error {err:.2e}")
+    assert status == 0 and true_res <= 1e-10 and err <= 1e-8
+    assert abs(info[0]["rel_residual"] - true_res) <= 1e-12
+
+
+def test_mixed_outer_settings():
+    from paper_1412_2629_amd import ddqcd
+    ctx = SMALL[2].context("f64")
+    with pytest.raises(ddqcd.DDQCDError):          # an FP64 preconditioner has no FP32 input
+        ctx.set_outer("fgcr_mixed")
+    ctx.set_sap(4, 5, "f32")
+    ctx.set_outer("fgcr_mixed")
+    with pytest.raises(ddqcd.DDQCDError):
+        ctx.set_sap(4, 5, "f64")
+    with pytest.raises(ddqcd.DDQCDError):
+        ctx.set_outer("fgcr_mixed", 2)
