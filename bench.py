@@ -34,12 +34,13 @@ CPU_BUDGET_S = 30.0          # bound on the oracle's host time
 
 # HBM bytes per half-sweep launch of the block-solve kernel, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE passes calibrated against a plain device copy
-# (profiles/k_sap_lds_16x16x16x32_f32.md, profiles/k_sap_lds_32x32x32x64_f16_and_uneven_batch.md).  They hold for the kernel sources
+# (profiles/k_sap_tile_32x32x32x64_12rhs_f16.md, profiles/k_sap_lds_32x32x32x64_f16_and_fgcr_blas.md).  They hold for the kernel sources
 # they were taken on, identified by a hash; after any change to those sources
 # the figure is reported as null until it is measured again.
+# Keyed by (workload, domain shape, product form).
 KERNEL_SOURCES = ("paper_1412_2629_amd/csrc/dd_sap.hip", "paper_1412_2629_amd/csrc/dd_device.h")
-MEASURED_TRAFFIC = {"C2": {"bytes_per_launch": 62.26e6, "sources": "6143a89311d60dc3"},
-                    "C3": {"bytes_per_launch": 599.84e6, "sources": "6143a89311d60dc3"}}
+MEASURED_TRAFFIC = {("C4", (4, 4, 4, 4), "tile"): {"bytes_per_launch": 5.1264e9, "sources": "bdf120db80f4d6bb"},
+                    ("C3", (8, 4, 4, 4), "lane"): {"bytes_per_launch": 602.66e6, "sources": "bdf120db80f4d6bb"}}
 
 
 def log(*a):
@@ -237,7 +238,7 @@ def main():
     dslash_gflops = dslash / (sap_ms * 1e-3) / 1e9
 
     traffic = None
-    m = MEASURED_TRAFFIC.get(args.workload)
+    m = MEASURED_TRAFFIC.get((args.workload, tuple(systems[0].w.domain), systems[0].product))
     if m and m["sources"] == kernel_sources_hash() and args.schwarz == "multiplicative":
         traffic = m["bytes_per_launch"]
 
