@@ -74,6 +74,26 @@ template <typename T> __device__ __forceinline__ cx<T> cmacc(cx<T> acc, cx<T> a,
     acc.i = fmad(-a.i, b.r, acc.i);
     return acc;
 }
+// -0.0 hidden from the compiler.  a * b + (-0.0) equals a * b exactly for
+// every a, b, so products written as fused multiply-adds onto it keep their
+// value, and the compiler cannot turn them back into multiplies: with
+// reduced-precision operands a multiply needs the operand converted first,
+// while a mixed-precision fused multiply-add takes it as stored.
+template <typename T> __device__ __forceinline__ T opaque_neg_zero()
+{
+    T z = T(-0.0);
+    asm("" : "+v"(z));
+    return z;
+}
+// a * b as fused multiply-adds onto -0.0 (the same value as a * b, see above)
+template <typename T> __device__ __forceinline__ cx<T> cmul_f(cx<T> a, cx<T> b, T z)
+{
+    return {fmad(a.r, b.r, -fmad(a.i, b.i, z)), fmad(a.r, b.i, fmad(a.i, b.r, z))};
+}
+template <typename T> __device__ __forceinline__ cx<T> cmulc_f(cx<T> a, cx<T> b, T z)
+{
+    return {fmad(a.r, b.r, fmad(a.i, b.i, z)), fmad(a.r, b.i, -fmad(a.i, b.r, z))};
+}
 template <typename T> __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
 template <typename T> __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
 template <typename T> __device__ __forceinline__ cx<T> neg(cx<T> a) { return {-a.r, -a.i}; }
@@ -123,22 +143,24 @@ __device__ __forceinline__ su3<T> ld_link(const v2<G> *p, long base, long stride
 // out[s][a] = sum_b U[a][b] h[s][b]   (two spin components of a half-spinor)
 template <typename T> __device__ __forceinline__ void su3_mul(const su3<T> &U, const cx<T> h[6], cx<T> out[6])
 {
+    const T z = opaque_neg_zero<T>();
 #pragma unroll
     for (int s = 0; s < 2; s++)
 #pragma unroll
         for (int a = 0; a < 3; a++)
-            out[s * 3 + a] = cmac(cmac(U.m[a * 3 + 0] * h[s * 3 + 0], U.m[a * 3 + 1], h[s * 3 + 1]), U.m[a * 3 + 2],
-                                  h[s * 3 + 2]);
+            out[s * 3 + a] = cmac(cmac(cmul_f(U.m[a * 3 + 0], h[s * 3 + 0], z), U.m[a * 3 + 1], h[s * 3 + 1]),
+                                  U.m[a * 3 + 2], h[s * 3 + 2]);
 }
 
 // out[s][a] = sum_b conj(U[b][a]) h[s][b]
 template <typename T> __device__ __forceinline__ void su3_dag_mul(const su3<T> &U, const cx<T> h[6], cx<T> out[6])
 {
+    const T z = opaque_neg_zero<T>();
 #pragma unroll
     for (int s = 0; s < 2; s++)
 #pragma unroll
         for (int a = 0; a < 3; a++)
-            out[s * 3 + a] = cmacc(cmacc(cmulc(U.m[0 * 3 + a], h[s * 3 + 0]), U.m[1 * 3 + a], h[s * 3 + 1]),
+            out[s * 3 + a] = cmacc(cmacc(cmulc_f(U.m[0 * 3 + a], h[s * 3 + 0], z), U.m[1 * 3 + a], h[s * 3 + 1]),
                                    U.m[2 * 3 + a], h[s * 3 + 2]);
 }
 

@@ -686,10 +686,12 @@ __device__ __forceinline__ void pair_block_solve(const SapArgs &a, const int d)
 template <typename T, typename G>
 __device__ __forceinline__ void clover_block_reg(const v2<G> *c, const cx<T> in[6], cx<T> out[6])
 {
+    const T z = opaque_neg_zero<T>();
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-        out[2 * q] = scal(static_cast<T>(c[q].x), in[2 * q]);
-        out[2 * q + 1] = scal(static_cast<T>(c[q].y), in[2 * q + 1]);
+        const T d0 = static_cast<T>(c[q].x), d1 = static_cast<T>(c[q].y);
+        out[2 * q] = {fmad(d0, in[2 * q].r, z), fmad(d0, in[2 * q].i, z)};
+        out[2 * q + 1] = {fmad(d1, in[2 * q + 1].r, z), fmad(d1, in[2 * q + 1].i, z)};
     }
 #pragma unroll
     for (int i = 1; i < 6; i++)
