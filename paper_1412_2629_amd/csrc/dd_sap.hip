@@ -1444,6 +1444,7 @@ __global__ __launch_bounds__(Sh::VH * RT) void k_sap_tile(const SapArgs *args, c
     __shared__ T red[NW * RT * 3];
 
     const int2 it = items[blockIdx.x];
+    if (it.x < 0) return;   // padding (XCD lists of unequal length)
     const int sys0 = it.x & 0xffffff, nt = it.x >> 24, d = it.y;
     const int t = threadIdx.x, hi = t >> 2, r = t & 3;
     // this lane's right-hand side; what the tile shares (geometry, links,
