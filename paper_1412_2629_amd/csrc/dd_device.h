@@ -113,6 +113,20 @@ template <typename T, typename S> __device__ __forceinline__ void st(v2<S> *p, l
     v.y = static_cast<S>(a.i);
     p[idx] = v;
 }
+// The same at a 32-bit byte offset from the array's base (arrays under 4 GiB):
+// one VGPR per address, and a uniform base can stay in SGPRs.
+template <typename T, typename S> __device__ __forceinline__ cx<T> ld32(const v2<S> *p, unsigned idx)
+{
+    const v2<S> v = *(const v2<S> *)((const char *)p + idx * (unsigned)sizeof(v2<S>));
+    return {static_cast<T>(v.x), static_cast<T>(v.y)};
+}
+template <typename T, typename S> __device__ __forceinline__ void st32(v2<S> *p, unsigned idx, cx<T> a)
+{
+    v2<S> v;
+    v.x = static_cast<S>(a.r);
+    v.y = static_cast<S>(a.i);
+    *(v2<S> *)((char *)p + idx * (unsigned)sizeof(v2<S>)) = v;
+}
 
 // ---- SU(3) ---------------------------------------------------------------
 
@@ -121,13 +135,13 @@ template <typename T> struct su3 {
 };
 
 // Loads U with NLC stored complex entries per link (9: all rows; 6: rows 0
-// and 1, row 2 rebuilt as conj(row0 x row1), exact for SU(3)).
-template <typename T, typename G, int NLC>
-__device__ __forceinline__ su3<T> ld_link(const v2<G> *p, long base, long stride)
+// and 1, row 2 rebuilt as conj(row0 x row1), exact for SU(3)); load(e)
+// returns stored entry e.
+template <typename T, int NLC, typename Load> __device__ __forceinline__ su3<T> ld_link_with(Load load)
 {
     su3<T> U;
 #pragma unroll
-    for (int e = 0; e < NLC; e++) U.m[e] = ld<T, G>(p, base + e * stride);
+    for (int e = 0; e < NLC; e++) U.m[e] = load(e);
     if constexpr (NLC == 6) {
         const cx<T> *a = U.m, *b = U.m + 3;
         U.m[6] = {a[1].r * b[2].r - a[1].i * b[2].i - a[2].r * b[1].r + a[2].i * b[1].i,
@@ -138,6 +152,12 @@ __device__ __forceinline__ su3<T> ld_link(const v2<G> *p, long base, long stride
                   -(a[0].r * b[1].i + a[0].i * b[1].r - a[1].r * b[0].i - a[1].i * b[0].r)};
     }
     return U;
+}
+
+template <typename T, typename G, int NLC>
+__device__ __forceinline__ su3<T> ld_link(const v2<G> *p, long base, long stride)
+{
+    return ld_link_with<T, NLC>([&](int e) { return ld<T, G>(p, base + e * stride); });
 }
 
 // out[s][a] = sum_b U[a][b] h[s][b]   (two spin components of a half-spinor)
@@ -225,14 +245,14 @@ __device__ __forceinline__ void recon_acc(cx<T> out[12], const cx<T> h[6], T k)
 
 __host__ __device__ constexpr int tri_index(int i, int j) { return i * (i - 1) / 2 + j; }  // i > j
 
-// out[0..5] (+)= M in[0..5] for one packed block starting at pair p0
-template <typename T, typename G>
-__device__ __forceinline__ void clover_block(const v2<G> *p, long base, long stride, const cx<T> in[6], cx<T> out[6])
+// out[0..5] = M in[0..5] for one packed block; load(q) returns its pair q
+template <typename T, typename Load>
+__device__ __forceinline__ void clover_block_with(Load load, const cx<T> in[6], cx<T> out[6])
 {
     T dg[6];
 #pragma unroll
     for (int q = 0; q < 3; q++) {
-        cx<T> v = ld<T, G>(p, base + q * stride);
+        cx<T> v = load(q);
         dg[2 * q] = v.r;
         dg[2 * q + 1] = v.i;
     }
@@ -242,10 +262,16 @@ __device__ __forceinline__ void clover_block(const v2<G> *p, long base, long str
     for (int i = 1; i < 6; i++)
 #pragma unroll
         for (int j = 0; j < i; j++) {
-            cx<T> m = ld<T, G>(p, base + (3 + tri_index(i, j)) * stride);
+            cx<T> m = load(3 + tri_index(i, j));
             out[i] = cmac(out[i], m, in[j]);
             out[j] = cmacc(out[j], m, in[i]);
         }
+}
+
+template <typename T, typename G>
+__device__ __forceinline__ void clover_block(const v2<G> *p, long base, long stride, const cx<T> in[6], cx<T> out[6])
+{
+    clover_block_with<T>([&](int q) { return ld<T, G>(p, base + q * stride); }, in, out);
 }
 
 template <typename T, typename G>

@@ -403,10 +403,172 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const v2<SI> *in, v2<SO>
     for (int k = 0; k < 12; k++) st<T, SO>(out, ((long)d * 12 + k) * Vd + loc, acc[k]);
 }
 
+// A on whole domains: workgroup = NT consecutive sites of the domain-blocked
+// order = NT / Vd whole domains.  The workgroup's input spinors are staged in
+// LDS, and each site pushes its backward term U_mu(x)^+ (1 + gamma_mu) psi(x)
+// to the site x + mu through LDS, so inside a domain every link and spinor
+// is read from memory once (by its own site); only hops that leave the
+// domain read a neighbour domain's spinor (and, backwards, its link).  The
+// hops are summed in the order of k_apply_A (per direction: forward, then
+// backward) with the same products, so both kernels give the same bits.
+// Field offsets are 32-bit byte offsets (the host checks that every field is
+// under 4 GiB), which keeps an address in one VGPR.
+template <int MU, int NT, typename T, typename SI, typename G, int NLC>
+__device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, int loc, int t, const v2<SI> *in,
+                                          const v2<G> *links, cx<T> (*sp)[NT], cx<T> (*ex)[NT], cx<T> acc[12])
+{
+    const unsigned Vd = (unsigned)g.Vd;
+    const int base = t - loc;                 // first thread of this site's domain
+    const int lx = x[MU] % g.b[MU];           // coordinate inside the domain
+    cx<T> h[6], uh[6];
+    {
+        const unsigned lb = ((unsigned)d * 4 + MU) * NLC * Vd + loc;
+        const su3<T> U = ld_link_with<T, NLC>([&](int e) { return ld32<T, G>(links, lb + e * Vd); });
+        // forward: -1/2 (1 - gamma_mu) U_mu(x) psi(x + mu)
+        {
+            cx<T> v[12];
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            bool wrap = false;
+            y[MU] = x[MU] + 1;
+            if (lx + 1 < g.b[MU]) {
+                const int lj = (int)(encode(g, y) - (long)d * Vd);
+#pragma unroll
+                for (int k = 0; k < 12; k++) v[k] = sp[k][base + lj];
+            } else {
+                if (y[MU] == g.L[MU]) { y[MU] = 0; wrap = true; }
+                const long J = encode(g, y);
+                const unsigned dj = (unsigned)(J / Vd), lj = (unsigned)(J - (long)dj * Vd);
+#pragma unroll
+                for (int k = 0; k < 12; k++) v[k] = ld32<T, SI>(in, (dj * 12 + k) * Vd + lj);
+            }
+            proj<MU, -1>(v, h);
+            su3_mul(U, h, uh);
+            recon_acc<MU, -1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
+        }
+        // push U_mu(x)^+ (1 + gamma_mu) psi(x) for the site x + mu
+        {
+            cx<T> v[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[k] = sp[k][t];
+            proj<MU, +1>(v, h);
+        }
+        su3_dag_mul(U, h, uh);
+#pragma unroll
+        for (int k = 0; k < 6; k++) ex[k][t] = uh[k];
+    }
+    __syncthreads();   // every push of this direction is in LDS
+    // backward: -1/2 (1 + gamma_mu) U_mu(x - mu)^+ psi(x - mu)
+    if (lx > 0) {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] = x[MU] - 1;
+        const int lj = (int)(encode(g, y) - (long)d * Vd);
+#pragma unroll
+        for (int k = 0; k < 6; k++) uh[k] = ex[k][base + lj];
+        recon_acc<MU, +1>(acc, uh, T(-0.5));
+    } else {
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] = x[MU] - 1;
+        bool wrap = false;
+        if (y[MU] < 0) { y[MU] = g.L[MU] - 1; wrap = true; }
+        const long J = encode(g, y);
+        const unsigned dj = (unsigned)(J / Vd), lj = (unsigned)(J - (long)dj * Vd);
+        cx<T> v[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = ld32<T, SI>(in, (dj * 12 + k) * Vd + lj);
+        proj<MU, +1>(v, h);
+        const unsigned lb = (dj * 4 + MU) * NLC * Vd + lj;
+        const su3<T> W = ld_link_with<T, NLC>([&](int e) { return ld32<T, G>(links, lb + e * Vd); });
+        su3_dag_mul(W, h, uh);
+        recon_acc<MU, +1>(acc, uh, T(wrap ? -0.5 * g.bc[MU] : -0.5));
+    }
+    __syncthreads();   // the pushes are consumed before the next direction's
+}
+
+template <int NT, typename T, typename SI, typename SO, typename G, int NLC>
+__global__ __launch_bounds__(NT, 2) void k_apply_A_dom(Geo g, const v2<SI> *in, v2<SO> *out, const v2<G> *links,
+                                                       const v2<G> *clov)
+{
+    __shared__ cx<T> sp[12][NT];   // the workgroup's input spinors
+    __shared__ cx<T> ex[6][NT];    // backward terms pushed to x + mu
+    // XCD-aware order as in k_apply_A: each XCD sweeps one contiguous eighth
+    const unsigned nbk = gridDim.x, w = blockIdx.x;
+    const unsigned blk = nbk % 8 == 0 ? (w % 8) * (nbk / 8) + w / 8 : w;
+    const int t = threadIdx.x;
+    const long I = (long)blk * NT + t;   // V is a multiple of NT: every thread has a site
+    int x[4], d, loc;
+    decode(g, I, x, d, loc);
+    const unsigned Vd = (unsigned)g.Vd;
+    cx<T> acc[12];
+    {
+        cx<T> s[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) s[k] = ld32<T, SI>(in, ((unsigned)d * 12 + k) * Vd + loc);
+#pragma unroll
+        for (int k = 0; k < 12; k++) sp[k][t] = s[k];
+        const unsigned cb = (unsigned)d * 36 * Vd + loc;
+        clover_block_with<T>([&](int q) { return ld32<T, G>(clov, cb + q * Vd); }, s, acc);
+        clover_block_with<T>([&](int q) { return ld32<T, G>(clov, cb + (18 + q) * Vd); }, s + 6, acc + 6);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int mu = 0; mu < 4; mu++) {
+        // the site's indices made opaque per direction: what is formed from
+        // them (neighbour indices, offsets) is formed here, not hoisted out of
+        // the loop and held in registers through it
+        int xs[4] = {x[0], x[1], x[2], x[3]}, ds = d, ls = loc, ts = t;
+        asm volatile("" : "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]), "+v"(ds), "+v"(ls), "+v"(ts));
+        switch (mu) {
+            case 0: a_dom_dir<0, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
+            case 1: a_dom_dir<1, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
+            case 2: a_dom_dir<2, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
+            default: a_dom_dir<3, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
+        }
+    }
+    {
+        int ds = d, ls = loc;   // output offsets formed here, not held through the hops
+        asm volatile("" : "+v"(ds), "+v"(ls));
+#pragma unroll
+        for (int k = 0; k < 12; k++) st32<T, SO>(out, ((unsigned)ds * 12 + k) * Vd + ls, acc[k]);
+    }
+}
+
+template <int NT>
+static void launch_apply_A_dom(const Geo &g, const void *in, void *out, const void *links, const void *clov,
+                               int prec, hipStream_t s)
+{
+    const unsigned nb = (unsigned)(g.V / NT);
+    if (prec == P64)
+        hipLaunchKernelGGL((k_apply_A_dom<NT, double, double, double, double, 9>), nb, NT, 0, s, g,
+                           (const double2 *)in, (double2 *)out, (const double2 *)links, (const double2 *)clov);
+    else if (prec == P32)
+        hipLaunchKernelGGL((k_apply_A_dom<NT, float, float, float, float, 6>), nb, NT, 0, s, g, (const float2 *)in,
+                           (float2 *)out, (const float2 *)links, (const float2 *)clov);
+    else if (prec == P16)
+        hipLaunchKernelGGL((k_apply_A_dom<NT, float, half_t, half_t, half_t, 6>), nb, NT, 0, s, g,
+                           (const half2_t *)in, (half2_t *)out, (const half2_t *)links, (const half2_t *)clov);
+    else
+        hipLaunchKernelGGL((k_apply_A_dom<NT, float, bf16_t, bf16_t, bf16_t, 6>), nb, NT, 0, s, g,
+                           (const bf162_t *)in, (bf162_t *)out, (const bf162_t *)links, (const bf162_t *)clov);
+}
+
 hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
                    hipStream_t s)
 {
     unsigned nb = nblocks(g.V, 256);
+    // whole domains per workgroup where the domain size divides the workgroup
+    // (2^4, 4^4: 256 threads; 8x4^3, 4^3x8: 512; V is then a multiple of it),
+    // for fields under 4 GiB (the largest, links and clover, hold 36 complex
+    // numbers per site)
+    const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+    const bool small = (size_t)g.V * 36 * elem < ((size_t)1 << 32);
+    if (small && g.Vd <= 256 && 256 % g.Vd == 0 && g.V % 256 == 0) {
+        launch_apply_A_dom<256>(g, in, out, links, clov, prec, s);
+        return hipGetLastError();
+    }
+    if (small && g.Vd == 512 && g.V % 512 == 0) {
+        launch_apply_A_dom<512>(g, in, out, links, clov, prec, s);
+        return hipGetLastError();
+    }
     if (prec == P64)
         hipLaunchKernelGGL((k_apply_A<double, double, double, double, 9>), nb, 256, 0, s, g, (const double2 *)in,
                            (double2 *)out, (const double2 *)links, (const double2 *)clov);
