@@ -25,7 +25,7 @@ def site_err(got, want):
     return float(np.linalg.norm(d) / np.linalg.norm(n)), float(d.max() / np.sqrt(np.mean(n * n)))
 
 
-# Block-solve output against the FP64 oracle (derivation in the design notes):
+# Block-solve output against the FP64 oracle:
 # FP32 arithmetic accumulates a few unit roundoffs per MR step; FP16 storage
 # rounds each stored link, clover entry, block residual and boundary term once
 # per half-sweep (BF16 storage likewise, with its u = 2^-8).  Each Schwarz
