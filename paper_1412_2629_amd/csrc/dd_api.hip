@@ -555,6 +555,28 @@ int apply_A64(ddqcd_t c, const double2 *in, double2 *out, hipStream_t s)
     return DDQCD_OK;
 }
 
+// out_i = A in_i (FP64) for the listed systems; two consecutive systems of one
+// context share a launch where the kernel allows it (each link and clover
+// load then serves both), with the bits of two single calls
+template <typename In, typename Out>
+int apply_A64_list(const std::vector<Sys> &sys, const std::vector<int> &list, In in_of, Out out_of, hipStream_t s)
+{
+    for (size_t q = 0; q < list.size();) {
+        const int i = list[q];
+        ddqcd_t c = sys[i].c;
+        if (q + 1 < list.size() && sys[list[q + 1]].c == c && apply_A_pairs(c->g, P64)) {
+            const int j = list[q + 1];
+            HIPCHK(c, apply_A_pair(c->g, in_of(i), out_of(i), in_of(j), out_of(j), c->U64, c->C64, P64, s));
+            q += 2;
+        } else {
+            const int e = apply_A64(c, in_of(i), out_of(i), s);
+            if (e) return e;
+            q += 1;
+        }
+    }
+    return DDQCD_OK;
+}
+
 // Phase timings of a solve: each phase is bracketed by two events on the
 // launch stream; the elapsed times are read once at the end (no extra
 // synchronisation between phases).
@@ -731,8 +753,10 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
     }
     {
         Timer t(clk, &tA);
-        for (int i : live)
-            if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
+        if ((e = apply_A64_list(
+                 sys, live, [&](int i) { return (const double2 *)sys[i].sl->x; }, [&](int i) { return sys[i].sl->r; },
+                 s)))
+            return e;
     }
     {
         Timer t(clk, &tother);
@@ -777,8 +801,10 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             // w_k = A z_k
             {
                 Timer t(clk, &tA);
-                for (int i : act)
-                    if ((e = apply_A64(sys[i].c, Zk(i, k), Wk(i, k), s))) return e;
+                if ((e = apply_A64_list(
+                         sys, act, [&](int i) { return (const double2 *)Zk(i, k); }, [&](int i) { return Wk(i, k); },
+                         s)))
+                    return e;
             }
             {
                 Timer t(clk, &tgs);
@@ -858,8 +884,10 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
         }
         {
             Timer t(clk, &tA);
-            for (int i : cur)
-                if ((e = apply_A64(sys[i].c, sys[i].sl->x, sys[i].sl->r, s))) return e;
+            if ((e = apply_A64_list(
+                     sys, cur, [&](int i) { return (const double2 *)sys[i].sl->x; },
+                     [&](int i) { return sys[i].sl->r; }, s)))
+                return e;
         }
         {
             Timer t(clk, &tother);

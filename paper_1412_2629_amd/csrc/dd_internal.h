@@ -29,6 +29,13 @@ hipError_t count_nonfinite(const double2 *v, long n, int *cnt, hipStream_t s);
 // out = A in (internal layouts; links/clover in the given precision).
 hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
                    hipStream_t s);
+// out0 = A in0 and out1 = A in1 on one lattice in one launch (the two
+// right-hand sides share each link and clover load); same bits as two apply_A
+// calls.  Available where apply_A_pairs(g, prec) (domains of at most 256
+// sites, fields under 4 GiB); hipErrorInvalidValue otherwise.
+bool apply_A_pairs(const Geo &g, int prec);
+hipError_t apply_A_pair(const Geo &g, const void *in0, void *out0, const void *in1, void *out1, const void *links,
+                        const void *clov, int prec, hipStream_t s);
 
 // What one visit of a domain reads and writes.
 struct Visit {

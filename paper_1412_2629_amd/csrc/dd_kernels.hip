@@ -403,22 +403,32 @@ __global__ __launch_bounds__(256) void k_apply_A(Geo g, const v2<SI> *in, v2<SO>
     for (int k = 0; k < 12; k++) st<T, SO>(out, ((long)d * 12 + k) * Vd + loc, acc[k]);
 }
 
-// A on whole domains: workgroup = NT consecutive sites of the domain-blocked
-// order = NT / Vd whole domains.  The workgroup's input spinors are staged in
-// LDS, and each site pushes its backward term U_mu(x)^+ (1 + gamma_mu) psi(x)
-// to the site x + mu through LDS, so inside a domain every link and spinor
-// is read from memory once (by its own site); only hops that leave the
-// domain read a neighbour domain's spinor (and, backwards, its link).  The
-// hops are summed in the order of k_apply_A (per direction: forward, then
-// backward) with the same products, so both kernels give the same bits.
-// Field offsets are 32-bit byte offsets (the host checks that every field is
-// under 4 GiB), which keeps an address in one VGPR.
-template <int MU, int NT, typename T, typename SI, typename G, int NLC>
-__device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, int loc, int t, const v2<SI> *in,
-                                          const v2<G> *links, cx<T> (*sp)[NT], cx<T> (*ex)[NT], cx<T> acc[12])
+// A on whole domains: a workgroup takes NT consecutive sites of the
+// domain-blocked order (NT / Vd whole domains) for R right-hand sides, one
+// thread per (site, right-hand side) with the R threads of a site adjacent,
+// so their link and clover loads are one request.  The workgroup's input
+// spinors are staged in LDS, and each site pushes its backward term
+// U_mu(x)^+ (1 + gamma_mu) psi(x) to the site x + mu through LDS, so inside a
+// domain every link and spinor is read from memory once (by its own site);
+// only hops that leave the domain read a neighbour domain's spinor (and,
+// backwards, its link).  The hops are summed in the order of k_apply_A (per
+// direction: forward, then backward) with the same products, so both kernels
+// give the same bits, for any R.  Field offsets are 32-bit byte offsets (the
+// host checks that every field is under 4 GiB), which keeps an address in
+// one VGPR.
+template <int R, typename SI, typename SO> struct RhsPtrs {
+    const v2<SI> *in[R];
+    v2<SO> *out[R];
+};
+
+template <int MU, int NT, int R, typename T, typename SI, typename G, int NLC>
+__device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, int loc, int ts, int r,
+                                          const v2<SI> *in, const v2<G> *links, cx<T> (*sp)[NT * R],
+                                          cx<T> (*ex)[NT * R], cx<T> acc[12])
 {
     const unsigned Vd = (unsigned)g.Vd;
-    const int base = t - loc;                 // first thread of this site's domain
+    const int base = ts - loc;                // first site of this site's domain in the workgroup
+    const int me = ts * R + r;                // this thread's LDS slot
     const int lx = x[MU] % g.b[MU];           // coordinate inside the domain
     cx<T> h[6], uh[6];
     {
@@ -433,7 +443,7 @@ __device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, i
             if (lx + 1 < g.b[MU]) {
                 const int lj = (int)(encode(g, y) - (long)d * Vd);
 #pragma unroll
-                for (int k = 0; k < 12; k++) v[k] = sp[k][base + lj];
+                for (int k = 0; k < 12; k++) v[k] = sp[k][(base + lj) * R + r];
             } else {
                 if (y[MU] == g.L[MU]) { y[MU] = 0; wrap = true; }
                 const long J = encode(g, y);
@@ -449,12 +459,12 @@ __device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, i
         {
             cx<T> v[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) v[k] = sp[k][t];
+            for (int k = 0; k < 12; k++) v[k] = sp[k][me];
             proj<MU, +1>(v, h);
         }
         su3_dag_mul(U, h, uh);
 #pragma unroll
-        for (int k = 0; k < 6; k++) ex[k][t] = uh[k];
+        for (int k = 0; k < 6; k++) ex[k][me] = uh[k];
     }
     __syncthreads();   // every push of this direction is in LDS
     // backward: -1/2 (1 + gamma_mu) U_mu(x - mu)^+ psi(x - mu)
@@ -463,7 +473,7 @@ __device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, i
         y[MU] = x[MU] - 1;
         const int lj = (int)(encode(g, y) - (long)d * Vd);
 #pragma unroll
-        for (int k = 0; k < 6; k++) uh[k] = ex[k][base + lj];
+        for (int k = 0; k < 6; k++) uh[k] = ex[k][(base + lj) * R + r];
         recon_acc<MU, +1>(acc, uh, T(-0.5));
     } else {
         int y[4] = {x[0], x[1], x[2], x[3]};
@@ -484,17 +494,25 @@ __device__ __forceinline__ void a_dom_dir(const Geo &g, const int x[4], int d, i
     __syncthreads();   // the pushes are consumed before the next direction's
 }
 
-template <int NT, typename T, typename SI, typename SO, typename G, int NLC>
-__global__ __launch_bounds__(NT, 2) void k_apply_A_dom(Geo g, const v2<SI> *in, v2<SO> *out, const v2<G> *links,
-                                                       const v2<G> *clov)
+template <int NT, int R, typename T, typename SI, typename SO, typename G, int NLC>
+__global__ __launch_bounds__(NT * R, 2) void k_apply_A_dom(Geo g, RhsPtrs<R, SI, SO> io, const v2<G> *links,
+                                                           const v2<G> *clov)
 {
-    __shared__ cx<T> sp[12][NT];   // the workgroup's input spinors
-    __shared__ cx<T> ex[6][NT];    // backward terms pushed to x + mu
+    __shared__ cx<T> sp[12][NT * R];   // the workgroup's input spinors
+    __shared__ cx<T> ex[6][NT * R];    // backward terms pushed to x + mu
     // XCD-aware order as in k_apply_A: each XCD sweeps one contiguous eighth
     const unsigned nbk = gridDim.x, w = blockIdx.x;
     const unsigned blk = nbk % 8 == 0 ? (w % 8) * (nbk / 8) + w / 8 : w;
-    const int t = threadIdx.x;
-    const long I = (long)blk * NT + t;   // V is a multiple of NT: every thread has a site
+    const int t = threadIdx.x, ts = t / R, r = t - ts * R;
+    const long I = (long)blk * NT + ts;   // V is a multiple of NT: every thread has a site
+    const v2<SI> *in = io.in[0];
+    v2<SO> *out = io.out[0];
+#pragma unroll
+    for (int q = 1; q < R; q++)
+        if (r == q) {
+            in = io.in[q];
+            out = io.out[q];
+        }
     int x[4], d, loc;
     decode(g, I, x, d, loc);
     const unsigned Vd = (unsigned)g.Vd;
@@ -515,13 +533,13 @@ __global__ __launch_bounds__(NT, 2) void k_apply_A_dom(Geo g, const v2<SI> *in, 
         // the site's indices made opaque per direction: what is formed from
         // them (neighbour indices, offsets) is formed here, not hoisted out of
         // the loop and held in registers through it
-        int xs[4] = {x[0], x[1], x[2], x[3]}, ds = d, ls = loc, ts = t;
-        asm volatile("" : "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]), "+v"(ds), "+v"(ls), "+v"(ts));
+        int xs[4] = {x[0], x[1], x[2], x[3]}, ds = d, ls = loc, tss = ts;
+        asm volatile("" : "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]), "+v"(ds), "+v"(ls), "+v"(tss));
         switch (mu) {
-            case 0: a_dom_dir<0, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
-            case 1: a_dom_dir<1, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
-            case 2: a_dom_dir<2, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
-            default: a_dom_dir<3, NT, T, SI, G, NLC>(g, xs, ds, ls, ts, in, links, sp, ex, acc); break;
+            case 0: a_dom_dir<0, NT, R, T, SI, G, NLC>(g, xs, ds, ls, tss, r, in, links, sp, ex, acc); break;
+            case 1: a_dom_dir<1, NT, R, T, SI, G, NLC>(g, xs, ds, ls, tss, r, in, links, sp, ex, acc); break;
+            case 2: a_dom_dir<2, NT, R, T, SI, G, NLC>(g, xs, ds, ls, tss, r, in, links, sp, ex, acc); break;
+            default: a_dom_dir<3, NT, R, T, SI, G, NLC>(g, xs, ds, ls, tss, r, in, links, sp, ex, acc); break;
         }
     }
     {
@@ -532,41 +550,63 @@ __global__ __launch_bounds__(NT, 2) void k_apply_A_dom(Geo g, const v2<SI> *in, 
     }
 }
 
-template <int NT>
-static void launch_apply_A_dom(const Geo &g, const void *in, void *out, const void *links, const void *clov,
-                               int prec, hipStream_t s)
+template <int NT, int R, typename T, typename S, int NLC>
+static void launch_A_dom(const Geo &g, const void *const *in, void *const *out, const void *links, const void *clov,
+                         hipStream_t s)
 {
-    const unsigned nb = (unsigned)(g.V / NT);
-    if (prec == P64)
-        hipLaunchKernelGGL((k_apply_A_dom<NT, double, double, double, double, 9>), nb, NT, 0, s, g,
-                           (const double2 *)in, (double2 *)out, (const double2 *)links, (const double2 *)clov);
-    else if (prec == P32)
-        hipLaunchKernelGGL((k_apply_A_dom<NT, float, float, float, float, 6>), nb, NT, 0, s, g, (const float2 *)in,
-                           (float2 *)out, (const float2 *)links, (const float2 *)clov);
-    else if (prec == P16)
-        hipLaunchKernelGGL((k_apply_A_dom<NT, float, half_t, half_t, half_t, 6>), nb, NT, 0, s, g,
-                           (const half2_t *)in, (half2_t *)out, (const half2_t *)links, (const half2_t *)clov);
-    else
-        hipLaunchKernelGGL((k_apply_A_dom<NT, float, bf16_t, bf16_t, bf16_t, 6>), nb, NT, 0, s, g,
-                           (const bf162_t *)in, (bf162_t *)out, (const bf162_t *)links, (const bf162_t *)clov);
+    RhsPtrs<R, S, S> io;
+    for (int q = 0; q < R; q++) {
+        io.in[q] = (const v2<S> *)in[q];
+        io.out[q] = (v2<S> *)out[q];
+    }
+    hipLaunchKernelGGL((k_apply_A_dom<NT, R, T, S, S, S, NLC>), (unsigned)(g.V / NT), NT * R, 0, s, g, io,
+                       (const v2<S> *)links, (const v2<S> *)clov);
+}
+
+template <int NT, int R>
+static void launch_apply_A_dom(const Geo &g, const void *const *in, void *const *out, const void *links,
+                               const void *clov, int prec, hipStream_t s)
+{
+    if (prec == P64) launch_A_dom<NT, R, double, double, 9>(g, in, out, links, clov, s);
+    else if (prec == P32) launch_A_dom<NT, R, float, float, 6>(g, in, out, links, clov, s);
+    else if (prec == P16) launch_A_dom<NT, R, float, half_t, 6>(g, in, out, links, clov, s);
+    else launch_A_dom<NT, R, float, bf16_t, 6>(g, in, out, links, clov, s);
+}
+
+// whole domains per workgroup where the domain size divides the workgroup's
+// site count (V is then a multiple of it) and every field is under 4 GiB (the
+// largest, links and clover, hold 36 complex numbers per site)
+static int dom_sites(const Geo &g, int prec)
+{
+    const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+    if ((size_t)g.V * 36 * elem >= ((size_t)1 << 32)) return 0;
+    if (g.Vd <= 256 && 256 % g.Vd == 0 && g.V % 256 == 0) return 256;
+    if (g.Vd == 512 && g.V % 512 == 0) return 512;
+    return 0;
+}
+
+bool apply_A_pairs(const Geo &g, int prec) { return dom_sites(g, prec) == 256; }
+
+hipError_t apply_A_pair(const Geo &g, const void *in0, void *out0, const void *in1, void *out1, const void *links,
+                        const void *clov, int prec, hipStream_t s)
+{
+    if (!apply_A_pairs(g, prec)) return hipErrorInvalidValue;
+    const void *in[2] = {in0, in1};
+    void *out[2] = {out0, out1};
+    launch_apply_A_dom<256, 2>(g, in, out, links, clov, prec, s);
+    return hipGetLastError();
 }
 
 hipError_t apply_A(const Geo &g, const void *in, void *out, const void *links, const void *clov, int prec,
                    hipStream_t s)
 {
     unsigned nb = nblocks(g.V, 256);
-    // whole domains per workgroup where the domain size divides the workgroup
-    // (2^4, 4^4: 256 threads; 8x4^3, 4^3x8: 512; V is then a multiple of it),
-    // for fields under 4 GiB (the largest, links and clover, hold 36 complex
-    // numbers per site)
-    const size_t elem = prec == P64 ? 16 : prec == P32 ? 8 : 4;
-    const bool small = (size_t)g.V * 36 * elem < ((size_t)1 << 32);
-    if (small && g.Vd <= 256 && 256 % g.Vd == 0 && g.V % 256 == 0) {
-        launch_apply_A_dom<256>(g, in, out, links, clov, prec, s);
-        return hipGetLastError();
-    }
-    if (small && g.Vd == 512 && g.V % 512 == 0) {
-        launch_apply_A_dom<512>(g, in, out, links, clov, prec, s);
+    const int nt = dom_sites(g, prec);
+    if (nt) {
+        const void *ins[1] = {in};
+        void *outs[1] = {out};
+        if (nt == 256) launch_apply_A_dom<256, 1>(g, ins, outs, links, clov, prec, s);
+        else launch_apply_A_dom<512, 1>(g, ins, outs, links, clov, prec, s);
         return hipGetLastError();
     }
     if (prec == P64)
