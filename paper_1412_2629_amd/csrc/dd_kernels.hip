@@ -40,8 +40,103 @@ template <typename S> __global__ void k_export_spinor(Geo g, const v2<S> *in, do
     for (int k = 0; k < 12; k++) st<double, double>(canon, c + k, ld<double, S>(in, ((long)d * 12 + k) * g.Vd + loc));
 }
 
+// The same conversions through LDS, one workgroup per domain of VD sites
+// (VD threads): the canonical side is moved as the domain's x-runs (b0 sites
+// x 12 components, contiguous in memory), consecutive threads on consecutive
+// 16-byte entries; the internal side one component at a time, consecutive
+// threads on consecutive sites.  buf holds the domain as [local lexicographic
+// site][12].
+__device__ __forceinline__ long dom_run_base(const Geo &g, int d, int j)
+{
+    // canonical index of the first site of x-run j (= (ly, lz, lt)) of domain d
+    int r = d, x[4];
+    x[0] = (r % g.n[0]) * g.b[0]; r /= g.n[0];
+    x[1] = (r % g.n[1]) * g.b[1]; r /= g.n[1];
+    x[2] = (r % g.n[2]) * g.b[2];
+    x[3] = (r / g.n[2]) * g.b[3];
+    x[1] += j % g.b[1]; j /= g.b[1];
+    x[2] += j % g.b[2];
+    x[3] += j / g.b[2];
+    return canon_index(g, x);
+}
+
+__device__ __forceinline__ int local_lex(const Geo &g, const int x[4])
+{
+    return x[0] % g.b[0] + g.b[0] * (x[1] % g.b[1] + g.b[1] * (x[2] % g.b[2] + g.b[2] * (x[3] % g.b[3])));
+}
+
+template <int VD, typename S> __global__ __launch_bounds__(VD) void k_import_dom(Geo g, const double2 *canon, v2<S> *out)
+{
+    __shared__ double2 buf[12 * VD];
+    const int d = blockIdx.x, t = threadIdx.x;
+    const int runlen = g.b[0] * 12;
+    for (int e = t; e < 12 * VD; e += VD) {
+        const int j = e / runlen, o = e - j * runlen;
+        buf[e] = canon[dom_run_base(g, d, j) * 12 + o];
+    }
+    __syncthreads();
+    int x[4], dd, loc;
+    decode(g, (long)d * VD + t, x, dd, loc);
+    const int ll = local_lex(g, x);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const double2 v = buf[ll * 12 + k];
+        st<double, S>(out, ((long)d * 12 + k) * VD + t, cx<double>{v.x, v.y});
+    }
+}
+
+template <int VD, typename S> __global__ __launch_bounds__(VD) void k_export_dom(Geo g, const v2<S> *in, double2 *canon)
+{
+    __shared__ double2 buf[12 * VD];
+    const int d = blockIdx.x, t = threadIdx.x;
+    int x[4], dd, loc;
+    decode(g, (long)d * VD + t, x, dd, loc);
+    const int ll = local_lex(g, x);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const cx<double> v = ld<double, S>(in, ((long)d * 12 + k) * VD + t);
+        buf[ll * 12 + k] = make_double2(v.r, v.i);
+    }
+    __syncthreads();
+    const int runlen = g.b[0] * 12;
+    for (int e = t; e < 12 * VD; e += VD) {
+        const int j = e / runlen, o = e - j * runlen;
+        canon[dom_run_base(g, d, j) * 12 + o] = buf[e];
+    }
+}
+
+template <int VD>
+static void launch_convert_dom(const Geo &g, const double *canon, void *internal, int prec, bool import,
+                               hipStream_t s)
+{
+    const unsigned nb = (unsigned)g.nd;
+    if (import) {
+        const double2 *c = (const double2 *)canon;
+        if (prec == P64) hipLaunchKernelGGL((k_import_dom<VD, double>), nb, VD, 0, s, g, c, (double2 *)internal);
+        else if (prec == P32) hipLaunchKernelGGL((k_import_dom<VD, float>), nb, VD, 0, s, g, c, (float2 *)internal);
+        else if (prec == P16) hipLaunchKernelGGL((k_import_dom<VD, half_t>), nb, VD, 0, s, g, c, (half2_t *)internal);
+        else hipLaunchKernelGGL((k_import_dom<VD, bf16_t>), nb, VD, 0, s, g, c, (bf162_t *)internal);
+    } else {
+        double2 *c = (double2 *)canon;
+        if (prec == P64) hipLaunchKernelGGL((k_export_dom<VD, double>), nb, VD, 0, s, g, (const double2 *)internal, c);
+        else if (prec == P32) hipLaunchKernelGGL((k_export_dom<VD, float>), nb, VD, 0, s, g, (const float2 *)internal, c);
+        else if (prec == P16) hipLaunchKernelGGL((k_export_dom<VD, half_t>), nb, VD, 0, s, g, (const half2_t *)internal, c);
+        else hipLaunchKernelGGL((k_export_dom<VD, bf16_t>), nb, VD, 0, s, g, (const bf162_t *)internal, c);
+    }
+}
+
+// domains of 256 or 512 sites through LDS, others one thread per site
+static bool convert_dom(const Geo &g, const double *canon, void *internal, int prec, bool import, hipStream_t s)
+{
+    if (g.Vd == 256) launch_convert_dom<256>(g, canon, internal, prec, import, s);
+    else if (g.Vd == 512) launch_convert_dom<512>(g, canon, internal, prec, import, s);
+    else return false;
+    return true;
+}
+
 hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int prec, hipStream_t s)
 {
+    if (convert_dom(g, canon, internal, prec, true, s)) return hipGetLastError();
     unsigned nb = nblocks(g.V, 256);
     if (prec == P64) hipLaunchKernelGGL(k_import_spinor<double>, nb, 256, 0, s, g, (const double2 *)canon, (double2 *)internal);
     else if (prec == P32) hipLaunchKernelGGL(k_import_spinor<float>, nb, 256, 0, s, g, (const double2 *)canon, (float2 *)internal);
@@ -52,6 +147,7 @@ hipError_t import_spinor(const Geo &g, const double *canon, void *internal, int 
 
 hipError_t export_spinor(const Geo &g, const void *internal, int prec, double *canon, hipStream_t s)
 {
+    if (convert_dom(g, canon, const_cast<void *>(internal), prec, false, s)) return hipGetLastError();
     unsigned nb = nblocks(g.V, 256);
     if (prec == P64) hipLaunchKernelGGL(k_export_spinor<double>, nb, 256, 0, s, g, (const double2 *)internal, (double2 *)canon);
     else if (prec == P32) hipLaunchKernelGGL(k_export_spinor<float>, nb, 256, 0, s, g, (const float2 *)internal, (double2 *)canon);
