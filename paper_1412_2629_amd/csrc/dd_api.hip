@@ -751,20 +751,30 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
             st[i].status = DDQCD_OK;
         } else live.push_back(i);
     }
+    // r = b - A x; from x = 0 that is b itself (A 0 = 0 exactly), a copy
+    std::vector<int> guessed;
+    {
+        Timer t(clk, &tother);
+        for (int i : live) {
+            if (guess[i]) guessed.push_back(i);
+            else HIPCHK(sys[i].c, hipMemcpyAsync(sys[i].sl->r, sys[i].sl->b, sizeof(double2) * nc(i),
+                                                 hipMemcpyDeviceToDevice, s));
+        }
+    }
     {
         Timer t(clk, &tA);
         if ((e = apply_A64_list(
-                 sys, live, [&](int i) { return (const double2 *)sys[i].sl->x; }, [&](int i) { return sys[i].sl->r; },
-                 s)))
+                 sys, guessed, [&](int i) { return (const double2 *)sys[i].sl->x; },
+                 [&](int i) { return sys[i].sl->r; }, s)))
             return e;
     }
     {
         Timer t(clk, &tother);
-        for (int i : live) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
-        if ((e = fetch_all(sys, st, live, 1, s))) return e;
+        for (int i : guessed) HIPCHK(sys[i].c, residual(sys[i].sl->blas, sys[i].sl->b, sys[i].sl->r, nc(i), s));
+        if (!guessed.empty() && (e = fetch_all(sys, st, guessed, 1, s))) return e;
     }
     for (int i : live) {
-        st[i].rel = std::sqrt(st[i].h[0].x) / st[i].bn;
+        st[i].rel = guess[i] ? std::sqrt(st[i].h[0].x) / st[i].bn : 1.0;
         if (!std::isfinite(st[i].rel)) return fail(sys[i].c, DDQCD_ERR_NONFINITE, "non-finite residual");
         if (st[i].rel <= tol) {
             st[i].done = true;
