@@ -1533,11 +1533,34 @@ int bicgstab(ddqcd_t c, Slot &sl, bool guess, int max_iter, ddqcd_info &info, hi
     HIPCHK(c, zero(p, n, s));
     HIPCHK(c, zero(v, n, s));
     C rho_old = 1, alpha = 1, omega = 1;
-    int it = 0, restarts = 0;
+    int it = 0, restarts = 0, breakdowns = 0;
+    // restart from the current x: r = b - A x (unless r already is), r0 = r,
+    // p = v = 0
+    auto restart = [&](bool have_r) -> int {
+        int e2;
+        if (!have_r) {
+            if ((e2 = apply_A64(c, x, r, s))) return e2;
+            HIPCHK(c, residual(sl.blas, b, r, n, s));
+            if ((e2 = fetch(1))) return e2;
+            rel = std::sqrt(h[0].x) / bn;
+        }
+        HIPCHK(c, lincomb(r0, r, one, r, zero2, nullptr, zero2, n, s));
+        HIPCHK(c, zero(p, n, s));
+        HIPCHK(c, zero(v, n, s));
+        rho_old = alpha = omega = 1;
+        restarts++;
+        return DDQCD_OK;
+    };
     while (rel > c->tol && it < max_iter) {
         C rho;
         if ((e = dot(r0, r, rho))) return e;
-        if (std::abs(rho) == 0 || std::abs(omega) == 0) return fail(c, DDQCD_ERR_NONFINITE, "BiCGstab breakdown");
+        if (std::abs(rho) == 0 || std::abs(omega) == 0) {
+            // breakdown (rho or omega vanished): restart from the current
+            // iterate with the true residual as the new shadow vector
+            if (++breakdowns > 100) return fail(c, DDQCD_ERR_NONFINITE, "BiCGstab breakdown");
+            if ((e = restart(false))) return e;
+            continue;
+        }
         const C beta = (rho / rho_old) * (alpha / omega);
         // p = r + beta (p - omega v)
         HIPCHK(c, lincomb(p, r, one, p, cd(beta), v, cd(-beta * omega), n, s));
@@ -1545,12 +1568,18 @@ int bicgstab(ddqcd_t c, Slot &sl, bool guess, int max_iter, ddqcd_info &info, hi
         C r0v;
         if ((e = dot(r0, v, r0v))) return e;
         alpha = rho / r0v;
+        if (!std::isfinite(alpha.real()) || !std::isfinite(alpha.imag())) {
+            // <r0, A p> vanished: restart before x takes the step
+            if (++breakdowns > 100) return fail(c, DDQCD_ERR_NONFINITE, "BiCGstab breakdown");
+            if ((e = restart(false))) return e;
+            continue;
+        }
         // s = r - alpha v, t = A s, omega = <t, s> / <t, t>
         HIPCHK(c, lincomb(sv, r, one, v, cd(-alpha), nullptr, zero2, n, s));
         if ((e = apply_A64(c, sv, t, s))) return e;
         HIPCHK(c, dot2(sl.blas, t, sv, n, s));
         if ((e = fetch(2))) return e;
-        omega = h[1].x > 0 ? C(h[0].x, h[0].y) / h[1].x : C(0);
+        omega = h[1].x > 0 && std::isfinite(h[0].x) && std::isfinite(h[0].y) ? C(h[0].x, h[0].y) / h[1].x : C(0);
         // x += alpha p + omega s, r = s - omega t
         HIPCHK(c, lincomb(x, x, one, p, cd(alpha), sv, cd(omega), n, s));
         HIPCHK(c, lincomb(r, sv, one, t, cd(-omega), nullptr, zero2, n, s));
@@ -1566,13 +1595,7 @@ int bicgstab(ddqcd_t c, Slot &sl, bool guess, int max_iter, ddqcd_info &info, hi
             HIPCHK(c, residual(sl.blas, b, r, n, s));
             if ((e = fetch(1))) return e;
             rel = std::sqrt(h[0].x) / bn;
-            if (rel > c->tol) {
-                restarts++;
-                HIPCHK(c, lincomb(r0, r, one, r, zero2, nullptr, zero2, n, s));
-                HIPCHK(c, zero(p, n, s));
-                HIPCHK(c, zero(v, n, s));
-                rho_old = alpha = omega = 1;
-            }
+            if (rel > c->tol && (e = restart(true))) return e;
         }
     }
     info.converged = rel <= c->tol;
