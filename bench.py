@@ -319,9 +319,12 @@ def main():
 
 def gram_schmidt_rate(systems, iters, runs):
     """Algorithmic HBM rate of FGCR's orthogonalisation (FP64 vectors, 192 B
-    per site): at step k of a cycle the multi-dot reads k + 2 vectors, the
-    update reads k + 2 and writes one, the normalisation reads and writes two;
-    divided by the Gram-Schmidt time the library measures on the stream."""
+    per site): at step k > 0 of a cycle the multi-dot reads the k earlier
+    columns and w, the update reads them, w and r and writes w, the residual
+    update reads w and r and writes r (2k + 7 vectors); at step 0 only <w, w>,
+    <w, r> (two reads) and the residual update (5 vectors).  Divided by the
+    Gram-Schmidt time the library measures on the stream (single passes: a
+    repeated pass adds bytes this does not count)."""
     byts = 0.0
     rhs = [s for s in systems for _ in s.srcs]
     for s, n in zip(rhs, iters):
@@ -329,7 +332,7 @@ def gram_schmidt_rate(systems, iters, runs):
         vec = s.w.volume * 192
         for step in range(n):
             k = step % m
-            byts += (2 * k + 9) * vec
+            byts += (2 * k + 7 if k > 0 else 5) * vec
     t_gs = sum(inf[0]["t_gs_ms"] for _, inf in runs) / len(runs)
     return {"algorithmic_GB": round(byts / 1e9, 3), "t_ms": round(t_gs, 3),
             "GB_per_s": round(byts / (t_gs * 1e-3) / 1e9, 1) if t_gs > 0 else None}

@@ -824,8 +824,9 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
                 std::vector<C> wr(ns);
                 std::vector<int> todo = act;
                 for (int pass = 0; pass < 2 && !todo.empty(); pass++) {
-                    // the first pass also takes <w, w> (column k of W is w itself)
-                    const int nd = pass == 0 ? k + 1 : k;
+                    // the first pass also takes <w, w> (column k of W is w itself),
+                    // which only the repeat test reads: not for the first vector
+                    const int nd = pass == 0 && k > 0 ? k + 1 : k;
                     if (nd > 0) {
                         for (int i : todo)
                             HIPCHK(sys[i].c, multidot(sys[i].sl->blas, sys[i].sl->W, nc(i), nd, Wk(i, k), nc(i), s));
@@ -833,10 +834,14 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
                         for (int i : todo) {
                             if (pass == 0) before[i] = st[i].h[k].x;
                             if (k == 0) continue;
+                            // the columns of W are kept unnormalised, W_j = b_j w-hat_j:
+                            // <w-hat_j, w> = <W_j, w> / b_j, and w -= sum <w-hat_j, w> w-hat_j
+                            // takes the coefficients <W_j, w> / b_j^2 on the columns
                             std::vector<C> coef(k);
                             for (int j = 0; j < k; j++) {
-                                coef[j] = C(st[i].h[j].x, st[i].h[j].y);
-                                st[i].a[(size_t)j * m + k] += coef[j];
+                                const C cj = C(st[i].h[j].x, st[i].h[j].y) / st[i].bb[j];
+                                st[i].a[(size_t)j * m + k] += cj;
+                                coef[j] = cj / st[i].bb[j];
                             }
                             if ((e = put_coef(sys[i], coef, s))) return e;
                         }
@@ -862,8 +867,10 @@ int fgcr(const std::vector<Sys> &sys, const std::vector<int> &guess, std::vector
                     if (!(f.bb[k] > 0) || !std::isfinite(f.bb[k]))
                         return fail(sys[i].c, DDQCD_ERR_NONFINITE, "breakdown: A M r vanished or is non-finite");
                     f.cc[k] = wr[i] / f.bb[k];
-                    HIPCHK(sys[i].c, normalize_update(sys[i].sl->blas, Wk(i, k), 1.0 / f.bb[k], sys[i].sl->r,
-                                                      make_double2(f.cc[k].real(), f.cc[k].imag()), nc(i), s));
+                    // r -= <w-hat, r> w-hat = (<w, r> / b^2) w; w stays unnormalised
+                    const C al = f.cc[k] / f.bb[k];
+                    HIPCHK(sys[i].c, residual_update(sys[i].sl->blas, Wk(i, k), sys[i].sl->r,
+                                                     make_double2(al.real(), al.imag()), nc(i), s));
                 }
                 if ((e = fetch_all(sys, st, act, 1, s))) return e;
             }

@@ -121,6 +121,8 @@ hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, co
                       hipStream_t s);
 // w *= inv_b; r -= c w; result[0] = (|r|^2, 0)
 hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s);
+// r -= c w; result[0] = (|r|^2, 0)
+hipError_t residual_update(Blas &B, const double2 *w, double2 *r, double2 c, long n, hipStream_t s);
 // x += sum_j coef[j] Z_j (coef on device, k <= 16)
 hipError_t axpy_multi(Blas &B, double2 *x, const double2 *Z, long ldz, int k, long n, hipStream_t s);
 // r = b - r; result[0] = (|r|^2, 0)

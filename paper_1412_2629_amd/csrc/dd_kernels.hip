@@ -894,6 +894,28 @@ hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, doubl
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(BS) void k_residual_update(const double2 *w, double2 *r, double2 c, long n,
+                                                        double2 *partial)
+{
+    double acc[2] = {0, 0};
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
+        const double2 x = w[i];
+        double2 y = r[i];
+        y.x -= c.x * x.x - c.y * x.y;
+        y.y -= c.x * x.y + c.y * x.x;
+        r[i] = y;
+        acc[0] += y.x * y.x + y.y * y.y;
+    }
+    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
+}
+
+hipError_t residual_update(Blas &B, const double2 *w, double2 *r, double2 c, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual_update, blas_blocks(n), BS, 0, s, w, r, c, n, B.partial);
+    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
+    return hipGetLastError();
+}
+
 template <int K> __global__ __launch_bounds__(BS) void k_axpy_multi(double2 *x, const double2 *Z, long ldz, const double2 *coef, long n)
 {
     double2 c[K];
