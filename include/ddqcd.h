@@ -308,7 +308,13 @@ int ddqcd_tune_domain(const int lattice[4], double kappa, double c_sw, const dou
  * (optional), its time in milliseconds to ms_out (optional; -1 when only one
  * pair fits and nothing was timed).  Allocates and frees its own device memory
  * (nrhs solution vectors and the candidates' contexts, one at a time).  Errors
- * as ddqcd_tune_domain. */
+ * as ddqcd_tune_domain.  When the environment variable DDQCD_TUNE_CACHE names
+ * a file, both calls keep their results there, one text line per problem, the
+ * key made of every argument above except b and stream, with a fingerprint of U
+ * (a hash of its first 64 numbers); a problem found in the file (whose pair is
+ * still a candidate) is answered from it without any timing, with the stored
+ * time; a new result is appended.  The file is read and appended with plain
+ * stdio: processes tuning at once may interleave lines. */
 int ddqcd_tune_sap(const int lattice[4], double kappa, double c_sw, const double boundary[4], const double *U,
                    const double *b, int nrhs, int prec, int n_cycles, int n_mr, int restart, double tol, int max_cycles,
                    int domain_out[4], int *product_out, double *ms_out, void *stream);

@@ -195,6 +195,27 @@ def test_tune_domain_respects_precision():
     assert dom in ((2, 2, 2, 2), (6, 6, 2, 4)) and ms > 0
 
 
+def test_tune_cache(tmp_path, monkeypatch):
+    """With DDQCD_TUNE_CACHE set, the first tuning times the candidates and
+    appends its result; the same problem again is answered from the file (same
+    pair and time, nothing appended); another gauge field is another key."""
+    from paper_1412_2629_amd import ddqcd, inputs
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("DDQCD_TUNE_CACHE", str(path))
+    case = SMALL[2]   # 8^4: 2^4 and 4^4 domains fit
+    f = dev(case.source(97))
+    U = dev(case.U)
+    dom1, ms1 = ddqcd.tune_domain(case.L, case.kappa, case.csw, U, f, prec="f16", n_cycles=4, n_mr=5)
+    assert ms1 > 0 and len(path.read_text().splitlines()) == 1
+    dom2, ms2 = ddqcd.tune_domain(case.L, case.kappa, case.csw, U, f, prec="f16", n_cycles=4, n_mr=5)
+    assert dom2 == dom1 and abs(ms2 - ms1) < 1e-5
+    assert len(path.read_text().splitlines()) == 1
+    U3 = dev(inputs.random_gauge(case.L, case.eps, 977))
+    dom3, ms3 = ddqcd.tune_domain(case.L, case.kappa, case.csw, U3, f, prec="f16", n_cycles=4, n_mr=5)
+    assert ms3 > 0 and dom3 in ((2, 2, 2, 2), (4, 4, 4, 4))
+    assert len(path.read_text().splitlines()) == 2
+
+
 def test_graph_batch_with_fp64_systems(oracle):
     from paper_1412_2629_amd import ddqcd
     a = SMALL[0].context()
