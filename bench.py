@@ -125,6 +125,41 @@ def solve_all(systems, ddqcd):
     return xs, infos
 
 
+def sap_work(systems, iters, additive=False):
+    """Algorithmic work of the block solves of one step: (flops, Dslash flops,
+    launches, bytes).  iters holds the outer steps of every right-hand side in
+    the order of the systems and their sources; each step is one
+    preconditioner call of n_cycles cycles visiting every domain once per
+    cycle.  Launches: two per cycle (one per colour; one for additive Schwarz)
+    per call, systems of one domain shape and precision sharing a launch, so
+    the group's longest system counts.  Bytes (geometry's byte model: links and
+    clover once per domain visit, spinor data per right-hand side): a system's
+    right-hand sides share its launches, so its longest right-hand side counts."""
+    from paper_1412_2629_amd import geometry
+    per_rhs = [s for s in systems for _ in s.srcs]
+    assert len(per_rhs) == len(iters)
+    flops = dslash = 0.0
+    groups, sys_iters = {}, {}
+    for s, it in zip(per_rhs, iters):
+        w = s.w
+        nd = w.volume // geometry.volume(w.domain)
+        pd = geometry.sap_flops_per_domain(w.domain, w.n_mr)
+        flops += it * pd["total"] * nd * w.n_cycles
+        dslash += it * pd["dslash"] * nd * w.n_cycles
+        key = (tuple(w.domain), w.prec)
+        groups[key] = max(groups.get(key, 0), it)
+        sys_iters[id(s)] = max(sys_iters.get(id(s), 0), it)
+    per_call = systems[0].w.n_cycles * (1 if additive else 2)
+    launches = sum(per_call * it for it in groups.values())
+    sap_bytes = 0.0
+    for s in systems:
+        w = s.w
+        nd = w.volume // geometry.volume(w.domain)
+        per = geometry.sap_bytes_per_domain(w.domain, w.prec if w.prec != "f64" else "f32", len(s.srcs))
+        sap_bytes += sys_iters[id(s)] * w.n_cycles * nd * per
+    return flops, dslash, launches, sap_bytes
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -213,37 +248,7 @@ def main():
         bb = torch.linalg.vector_norm(s.b.reshape(len(s.srcs), -1), dim=1)
         true_res = max(true_res, float((rr / bb).max()))
 
-    # algorithmic SAP work of the step: every right-hand side, every
-    # preconditioner call it made (one per FGCR step)
-    per_rhs = [(s, k) for s in systems for k in range(len(s.srcs))]
-    flops = dslash = launches = 0.0
-    for (s, _), it in zip(per_rhs, iters):
-        w = s.w
-        nd = w.volume // geometry.volume(w.domain)
-        pd = geometry.sap_flops_per_domain(w.domain, w.n_mr)
-        flops += it * pd["total"] * nd * w.n_cycles
-        dslash += it * pd["dslash"] * nd * w.n_cycles
-    # launches: 2 per cycle per preconditioner call; systems of one domain
-    # shape and precision share a launch, so count the calls of the longest
-    # system per group
-    groups = {}
-    for (s, _), it in zip(per_rhs, iters):
-        key = (s.w.domain, s.w.prec)
-        groups[key] = max(groups.get(key, 0), it)
-    per_call = systems[0].w.n_cycles * (1 if args.schwarz == "additive" else 2)
-    launches = sum(per_call * it for it in groups.values())
-    # algorithmic bytes of the same calls (geometry's byte model: links and
-    # clover once per domain visit, spinor data per right-hand side; the
-    # right-hand sides of one system share its launches)
-    sys_iters = {}
-    for (s, _), it in zip(per_rhs, iters):
-        sys_iters[id(s)] = max(sys_iters.get(id(s), 0), it)
-    sap_bytes = 0.0
-    for s in systems:
-        w = s.w
-        nd = w.volume // geometry.volume(w.domain)
-        per = geometry.sap_bytes_per_domain(w.domain, w.prec if w.prec != "f64" else "f32", len(s.srcs))
-        sap_bytes += sys_iters[id(s)] * w.n_cycles * nd * per
+    flops, dslash, launches, sap_bytes = sap_work(systems, iters, args.schwarz == "additive")
     sap_ms = sum(i["t_sap_ms"] for _, inf in runs for i in inf[:1]) / len(runs)
     launch_ms = sap_ms / launches
     achieved_tflops = flops / (sap_ms * 1e-3) / 1e12
