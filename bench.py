@@ -309,6 +309,7 @@ def main():
         "time_split_ms": {k: round(sum(inf[0][k] for _, inf in runs) / len(runs), 3)
                           for k in ("t_sap_ms", "t_A_ms", "t_gs_ms", "t_other_ms")},
         "fgcr_gram_schmidt": gram_schmidt_rate(systems, iters, runs),
+        "global_operator": operator_rate(systems, iters, runs),
         "sap_dslash_gflops": round(dslash_gflops, 1),
         "sap_total_tflops": round(achieved_tflops, 3),
         "sap_launches_per_step": int(launches),
@@ -341,6 +342,25 @@ def gram_schmidt_rate(systems, iters, runs):
     t_gs = sum(inf[0]["t_gs_ms"] for _, inf in runs) / len(runs)
     return {"algorithmic_GB": round(byts / 1e9, 3), "t_ms": round(t_gs, 3),
             "GB_per_s": round(byts / (t_gs * 1e-3) / 1e9, 1) if t_gs > 0 else None}
+
+
+def operator_rate(systems, iters, runs):
+    """Algorithmic HBM rate of the outer solver's FP64 operator applications:
+    one per FGCR step (w = A z) and one true residual per restart cycle (from a
+    zero start the first residual is b itself), 1536 bytes per site each
+    (spinor in and out, links and clover); divided by the operator time the
+    library measures on the stream."""
+    byts = 0.0
+    calls = 0
+    rhs = [s for s in systems for _ in s.srcs]
+    for s, n in zip(rhs, iters):
+        m = s.w.restart
+        c = n + (n + m - 1) // m
+        calls += c
+        byts += c * s.w.volume * 1536
+    t_a = sum(inf[0]["t_A_ms"] for _, inf in runs) / len(runs)
+    return {"applications": calls, "algorithmic_GB": round(byts / 1e9, 3), "t_ms": round(t_a, 3),
+            "GB_per_s": round(byts / (t_a * 1e-3) / 1e9, 1) if t_a > 0 else None}
 
 
 def roofline(systems, achieved_tflops, sap_bytes, sap_ms, launches, traffic):

@@ -75,3 +75,15 @@ def test_gram_schmidt_byte_model():
     g = bench.gram_schmidt_rate([s], [17], runs)
     want = (5 + sum(2 * k + 7 for k in range(1, 16)) + 5) * vec
     assert g["algorithmic_GB"] == pytest.approx(want / 1e9, abs=1e-3)
+
+
+def test_operator_byte_model():
+    """One application per outer step and one true residual per restart
+    cycle, 1536 bytes per site each."""
+    s = system((32, 32, 32, 64), (4, 4, 4, 4), "f16", 2)
+    runs = [(None, [{"t_A_ms": 4.0}])]
+    g = bench.operator_rate([s], [3, 17], runs)
+    calls = (3 + 1) + (17 + 2)
+    assert g["applications"] == calls
+    assert g["algorithmic_GB"] == pytest.approx(calls * 32 ** 3 * 64 * 1536 / 1e9, abs=1e-3)
+    assert g["GB_per_s"] == pytest.approx(calls * 32 ** 3 * 64 * 1536 / 4e-3 / 1e9, rel=1e-3)
