@@ -119,8 +119,6 @@ hipError_t multidot(Blas &B, const double2 *W, long ldw, int k, const double2 *v
 // w -= sum_j coef[j] W_j (coef on device, k <= 16); result[0] = (|w|^2, 0), result[1] = <w, r>
 hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, const double2 *r, long n,
                       hipStream_t s);
-// w *= inv_b; r -= c w; result[0] = (|r|^2, 0)
-hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s);
 // r -= c w; result[0] = (|r|^2, 0)
 hipError_t residual_update(Blas &B, const double2 *w, double2 *r, double2 c, long n, hipStream_t s);
 // x += sum_j coef[j] Z_j (coef on device, k <= 16)

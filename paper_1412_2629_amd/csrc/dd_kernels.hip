@@ -870,30 +870,6 @@ hipError_t cgs_update(Blas &B, double2 *w, const double2 *W, long ldw, int k, co
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(BS) void k_normalize_update(double2 *w, double inv_b, double2 *r, double2 c, long n, double2 *partial)
-{
-    double acc[2] = {0, 0};
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) {
-        double2 x = w[i];
-        x.x *= inv_b;
-        x.y *= inv_b;
-        w[i] = x;
-        double2 y = r[i];
-        y.x -= c.x * x.x - c.y * x.y;
-        y.y -= c.x * x.y + c.y * x.x;
-        r[i] = y;
-        acc[0] += y.x * y.x + y.y * y.y;
-    }
-    block_reduce_store<2>(acc, partial + (long)blockIdx.x * 32);
-}
-
-hipError_t normalize_update(Blas &B, double2 *w, double inv_b, double2 *r, double2 c, long n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_normalize_update, blas_blocks(n), BS, 0, s, w, inv_b, r, c, n, B.partial);
-    hipLaunchKernelGGL(k_finish, 1, BS, 0, s, B.partial, blas_blocks(n), 1, B.result);
-    return hipGetLastError();
-}
-
 __global__ __launch_bounds__(BS) void k_residual_update(const double2 *w, double2 *r, double2 c, long n,
                                                         double2 *partial)
 {
