@@ -147,6 +147,24 @@ def test_sap_fullsize(name, precs, oracle):
         check_sap(host(ctx.sap(dev(eta))), want, prec, f"{name} ({w.domain} domains, {w.n_cycles}x{w.n_mr})")
 
 
+@pytest.mark.timeout(600)
+def test_sap_fullsize_tile(oracle):
+    """The 12-source benchmark's block solves: tiles of right-hand sides on 4^4
+    domains of the 32^3x64 lattice (FP16 storage, 16 x 5), two Gaussian
+    right-hand sides in one tile against the oracle's SAP of each."""
+    import dataclasses
+    _, U, _ = fields("C3")   # the 12-source workload shares this gauge field
+    w = dataclasses.replace(configs.WORKLOADS["C4"], domain=(4, 4, 4, 4))
+    C, Ci = oracle_clover("C3")
+    etas = np.stack([inputs.gaussian_source(w.lattice, w.source_seed + 70 + k) for k in range(2)])
+    ctx = context(w, U)
+    ctx.set_sap(w.n_cycles, w.n_mr, "f16", "tile")
+    got = host(ctx.sap(dev(etas)))
+    for k in range(2):
+        want = oracle.sap(w.lattice, w.domain, w.bc, U, C, Ci, w.n_cycles, w.n_mr, etas[k])
+        check_sap(got[k], want, "f16", f"32^3x64 tile, rhs {k} (4^4 domains, {w.n_cycles}x{w.n_mr})")
+
+
 # ---------------------------------------------------------------------------
 # solves
 # ---------------------------------------------------------------------------
