@@ -1274,9 +1274,13 @@ template <int NW, int N> __device__ __forceinline__ void rhs_sum(float (&v)[N], 
         for (int k = 0; k < NW; k++) s += red[(k * RT + r) * N + q];
         v[q] = s;
     }
-    __syncthreads();
+    // no closing barrier: the MR step's next two barriers pass before red is
+    // written again (the next step's sums, or the epilogue's maxima)
 }
 
+// The maximum of v over the workgroup for this lane's right-hand side, through
+// red[0 .. NW * RT); no closing barrier: the callers (the epilogue) give each
+// maximum its own part of red and write none of it again.
 template <int NW> __device__ __forceinline__ float rhs_max(float v, float *red)
 {
 #pragma unroll
@@ -1286,7 +1290,6 @@ template <int NW> __device__ __forceinline__ float rhs_max(float v, float *red)
     __syncthreads();
     float m = red[r];
     for (int k = 1; k < NW; k++) m = fmax(m, red[k * RT + r]);
-    __syncthreads();
     return m;
 }
 
@@ -1661,7 +1664,7 @@ __global__ __launch_bounds__(Sh::VH * RT) void k_sap_tile(const SapArgs *args, c
     if (v.faces_out) {
         T sc = T(1);
         if constexpr (SCALED) {
-            sc = T(8) * pow2_ceil(rhs_max<NW>(fmax(maxabs12(Ae), maxabs12(Ao)), red));
+            sc = T(8) * pow2_ceil(rhs_max<NW>(fmax(maxabs12(Ae), maxabs12(Ao)), red + NW * RT));
             if (hi == 0 && live) a.face_scale[d] = (float)sc;
         }
         const T inv = T(1) / sc;
